@@ -1,0 +1,494 @@
+// sps_api.hip -- host runtime behind the C ABI of include/sps.h.
+//
+// A sketch is one device block: [scan counters | info words | SRE array | SLE array |
+// hot bitmap | HSE lists | candidates | kept hosts | ordered results].  The SRE and SLE
+// arrays are contiguous, so reset and merge treat them as one flat u16 range.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stddef.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+#include "sps_internal.h"
+
+using sps::Ctrl;
+using sps::Dev;
+
+struct sps_sketch {
+  sps_params p;
+  Dev dev;
+  sps::MlpRef mlp;
+  void* base;
+  bool owns;
+  size_t bytes;
+  uint16_t* state;        // == dev.sre; SRE then SLE array, contiguous
+  uint64_t state_cells;   // u16 cells of SRE + SLE arrays (incl. row padding)
+  uint64_t sre_cells;
+  uint32_t* d_info;       // SPS_INFO_WORDS u32
+  sps_result* d_sorted;   // cand_cap results (synchronous scan target)
+  uint32_t* h_info;       // pinned SPS_INFO_WORDS u32
+  uint32_t cur;
+  int device;
+  int n_cu;
+  int ingest_blocks;
+};
+
+namespace {
+
+thread_local char g_hip_detail[256] = "";
+
+int hip_fail(hipError_t e, const char* where) {
+  snprintf(g_hip_detail, sizeof(g_hip_detail), "%s: %s", where, hipGetErrorString(e));
+  return SPS_EHIP;
+}
+
+#define SPS_HIP(call)                              \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+bool is_pow2(uint64_t v) { return v != 0 && (v & (v - 1)) == 0; }
+uint32_t log2u(uint64_t v) {
+  uint32_t n = 0;
+  while ((1ull << n) < v) ++n;
+  return n;
+}
+uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+uint32_t effective_cand_cap(const sps_params* p) { return p->cand_cap ? p->cand_cap : (1u << 18); }
+
+int validate(const sps_params* p) {
+  if (!p) return SPS_EINVAL;
+  if (p->q < 6 || p->q > 24 || p->r < 3 || p->r > (uint32_t)sps::kMaxR) return SPS_EINVAL;
+  if (p->delta < 1 || p->delta >= p->q) return SPS_EINVAL;
+  if ((uint64_t)(p->r - 2) * p->delta + p->q < 32) return SPS_EINVAL;  // every bit recovered
+  if ((uint64_t)(p->r - 2) * p->delta > 31) return SPS_EINVAL;
+  if (!(p->eta == 8 || p->eta == 16 || p->eta == 32 || p->eta == 64)) return SPS_EINVAL;
+  if (p->qp < 1 || p->qp > 26 || p->rp < 1 || p->rp > (uint32_t)sps::kMaxRP) return SPS_EINVAL;
+  if (!is_pow2(p->etap) || p->etap < 16 || p->etap > 65536) return SPS_EINVAL;
+  if (!is_pow2(p->deltap) || p->deltap > p->etap) return SPS_EINVAL;
+  if (p->qp + log2u(p->deltap) > 31) return SPS_EINVAL;  // row live counts fit u32
+  if (p->theta < 1 || p->anet_side > 1) return SPS_EINVAL;
+  if (effective_cand_cap(p) > (1u << 26)) return SPS_EINVAL;
+  return SPS_OK;
+}
+
+// Sampling depth, Eq. 1 in integer form: smallest t with eta * 2^t >= theta.
+uint32_t sampling_depth(uint32_t theta, uint32_t eta) {
+  uint32_t t = 0;
+  while (((uint64_t)eta << t) < theta) ++t;
+  return t;
+}
+
+// Hot cut of Sec. 3.2: weight >= rho * eta with rho = 0.99 (1 - e^(-1/3)).
+uint32_t hot_cut_of(uint32_t eta) {
+  const double rho = 0.99 * (1.0 - exp(-1.0 / 3.0));
+  return (uint32_t)ceil(rho * (double)eta);
+}
+
+// SplitMix64 step; seed j of the sketch is the low word of output j.
+uint64_t splitmix64_next(uint64_t& st) {
+  st += 0x9E3779B97F4A7C15ull;
+  uint64_t z = st;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct Layout {
+  uint64_t ctrl, info, sre, slea, hot, hse, cand, kept, sorted, total;
+  uint64_t row_len, row_stride, sre_cells, slea_cells;
+};
+
+Layout layout_of(const sps_params* p) {
+  Layout L{};
+  const uint64_t cap = effective_cand_cap(p);
+  L.row_len = ((uint64_t)1 << p->qp) * p->deltap + p->etap - p->deltap;
+  L.row_stride = round_up(L.row_len, 128);  // 256-byte rows, whole u16x8 vectors
+  L.sre_cells = ((uint64_t)p->r << p->q) * p->eta;
+  L.slea_cells = (uint64_t)p->rp * L.row_stride;
+  uint64_t o = 0;
+  L.ctrl = o;   o += sizeof(Ctrl);
+  L.info = o;   o += 256;
+  L.sre = o;    o += round_up(L.sre_cells * 2, 256);
+  L.slea = o;   o += round_up(L.slea_cells * 2, 256);
+  L.hot = o;    o += round_up(((uint64_t)p->r << p->q) / 8, 256);
+  L.hse = o;    o += round_up(((uint64_t)2 << p->q) * 4, 256);
+  L.cand = o;   o += round_up(cap * 4, 256);
+  L.kept = o;   o += round_up(cap * sizeof(sps_result), 256);
+  L.sorted = o; o += round_up(cap * sizeof(sps_result), 256);
+  L.total = o;
+  return L;
+}
+
+bool same_shape(const sps_params& a, const sps_params& b) {
+  return a.q == b.q && a.r == b.r && a.delta == b.delta && a.eta == b.eta && a.qp == b.qp &&
+         a.rp == b.rp && a.etap == b.etap && a.deltap == b.deltap && a.theta == b.theta &&
+         a.anet_side == b.anet_side && a.seed == b.seed;
+}
+
+int check_slice(const sps_sketch* s, uint32_t slice) {
+  if (slice < 1 || slice > 65534u || slice < s->cur) return SPS_ESLICE;
+  return SPS_OK;
+}
+
+struct Header {  // 64-byte dump header
+  char magic[4];
+  uint32_t cur;
+  sps_params p;
+};
+static_assert(sizeof(Header) == 64, "dump header is 64 bytes");
+
+}  // namespace
+
+extern "C" {
+
+const char* sps_strerror(int code) {
+  switch (code) {
+    case SPS_OK: return "ok";
+    case SPS_EINVAL: return "invalid argument or unsupported sketch parameters";
+    case SPS_ESLICE: return "slice out of order or out of range (1..65534, >= current slice)";
+    case SPS_EMISMATCH: return "sketch parameters or seeds differ";
+    case SPS_ENOMEM: return "out of device memory or caller block too small";
+    case SPS_ECAPACITY: return "result or candidate buffer too small";
+    case SPS_EHIP: return g_hip_detail[0] ? g_hip_detail : "HIP runtime error";
+    case SPS_EBUDGET: return "device-memory budget exhausted";
+    default: return "unknown error";
+  }
+}
+
+int sps_sketch_bytes(const sps_params* p, size_t* bytes) {
+  if (!bytes) return SPS_EINVAL;
+  int rc = validate(p);
+  if (rc) return rc;
+  *bytes = (size_t)layout_of(p).total;
+  return SPS_OK;
+}
+
+int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out) {
+  if (!out) return SPS_EINVAL;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  const Layout L = layout_of(p);
+  if (d_mem && (bytes < L.total || ((uintptr_t)d_mem & 255u))) return SPS_ENOMEM;
+  int device = 0, n_cu = 0;
+  SPS_HIP(hipGetDevice(&device));
+  SPS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+  sps_sketch* s = new (std::nothrow) sps_sketch();
+  if (!s) return SPS_ENOMEM;
+  s->p = *p;
+  s->p.cand_cap = effective_cand_cap(p);
+  s->device = device;
+  s->n_cu = n_cu;
+  if (d_mem) {
+    s->base = d_mem;
+    s->owns = false;
+  } else {
+    if (hipMalloc(&s->base, L.total) != hipSuccess) {
+      delete s;
+      return SPS_ENOMEM;
+    }
+    s->owns = true;
+  }
+  if (hipHostMalloc((void**)&s->h_info, 256, hipHostMallocDefault) != hipSuccess) {
+    if (s->owns) (void)hipFree(s->base);
+    delete s;
+    return SPS_ENOMEM;
+  }
+  s->bytes = L.total;
+  uint8_t* b = static_cast<uint8_t*>(s->base);
+  Dev& d = s->dev;
+  d.ctrl = reinterpret_cast<Ctrl*>(b + L.ctrl);
+  d.sre = reinterpret_cast<uint16_t*>(b + L.sre);
+  d.slea = reinterpret_cast<uint16_t*>(b + L.slea);
+  d.hot = reinterpret_cast<uint32_t*>(b + L.hot);
+  d.hse = reinterpret_cast<uint32_t*>(b + L.hse);
+  d.cand = reinterpret_cast<uint32_t*>(b + L.cand);
+  d.kept = reinterpret_cast<sps_result*>(b + L.kept);
+  s->d_info = reinterpret_cast<uint32_t*>(b + L.info);
+  s->d_sorted = reinterpret_cast<sps_result*>(b + L.sorted);
+  d.row_len = L.row_len;
+  d.row_stride = L.row_stride;
+  d.q = p->q;
+  d.r = p->r;
+  d.delta = p->delta;
+  d.eta = p->eta;
+  d.qp = p->qp;
+  d.rp = p->rp;
+  d.etap = p->etap;
+  d.deltap = p->deltap;
+  const uint32_t tau = sampling_depth(p->theta, p->eta);
+  d.tau_mask = tau >= 32 ? 0xFFFFFFFFu : ((1u << tau) - 1u);
+  d.hot_cut = hot_cut_of(p->eta);
+  d.anet_side = p->anet_side;
+  d.cand_cap = s->p.cand_cap;
+  uint64_t st = p->seed;
+  d.seed_h1 = (uint32_t)splitmix64_next(st);
+  d.seed_h2 = (uint32_t)splitmix64_next(st);
+  d.seed_h3 = (uint32_t)splitmix64_next(st);
+  d.seed_rhfg0 = (uint32_t)splitmix64_next(st);
+  for (int i = 0; i < sps::kMaxRP; ++i) d.seed_lh[i] = (uint32_t)splitmix64_next(st);
+  s->state = d.sre;
+  s->sre_cells = L.sre_cells;
+  s->state_cells = (L.slea - L.sre) / 2 + L.slea_cells;
+  s->cur = 0;
+  s->mlp.w = nullptr;
+  s->ingest_blocks = s->n_cu * 16;
+  // zero state and workspace once, synchronously
+  SPS_HIP(hipMemset(s->base, 0, L.total));
+  SPS_HIP(hipDeviceSynchronize());
+  *out = s;
+  return SPS_OK;
+}
+
+int sps_destroy(sps_sketch* s) {
+  if (!s) return SPS_EINVAL;
+  (void)hipDeviceSynchronize();
+  if (s->owns) (void)hipFree(s->base);
+  (void)hipHostFree(s->h_info);
+  delete s;
+  return SPS_OK;
+}
+
+int sps_reset(sps_sketch* s, void* stream) {
+  if (!s) return SPS_EINVAL;
+  SPS_HIP(sps::launch_fill_zero(s->state, s->state_cells * 2, (hipStream_t)stream));
+  s->cur = 0;
+  return SPS_OK;
+}
+
+int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, void* stream) {
+  if (!s || (n && !d_pkts)) return SPS_EINVAL;
+  int rc = check_slice(s, slice);
+  if (rc) return rc;
+  SPS_HIP(sps::launch_ingest(s->dev, d_pkts, n, (uint16_t)slice, s->ingest_blocks, 256,
+                             (hipStream_t)stream));
+  s->cur = slice;
+  return SPS_OK;
+}
+
+int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
+                       uint32_t m, uint32_t slice, void* stream) {
+  if (!h_s || !h_pkts || !h_n || m == 0) return SPS_EINVAL;
+  for (uint32_t j = 0; j < m; ++j) {
+    if (!h_s[j] || (h_n[j] && !h_pkts[j])) return SPS_EINVAL;
+    if (!same_shape(h_s[j]->p, h_s[0]->p)) return SPS_EMISMATCH;
+    int rc = check_slice(h_s[j], slice);
+    if (rc) return rc;
+  }
+  const uint32_t tile = 4096;
+  for (uint32_t b = 0; b < m; b += sps::kMaxBatch) {
+    const uint32_t k = m - b < (uint32_t)sps::kMaxBatch ? m - b : (uint32_t)sps::kMaxBatch;
+    sps::BatchTable t{};
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+      t.item[j].sre = h_s[b + j]->dev.sre;
+      t.item[j].slea = h_s[b + j]->dev.slea;
+      t.item[j].pkts = h_pkts[b + j];
+      t.item[j].n = h_n[b + j];
+      t.tile_start[j] = acc;
+      acc += (h_n[b + j] + tile - 1) / tile;
+    }
+    t.tile_start[k] = acc;
+    SPS_HIP(sps::launch_ingest_batched(h_s[0]->dev, t, k, tile, (uint16_t)slice,
+                                       h_s[0]->n_cu * 16, 256, (hipStream_t)stream));
+  }
+  for (uint32_t j = 0; j < m; ++j) h_s[j]->cur = slice;
+  return SPS_OK;
+}
+
+int sps_advance(sps_sketch* s, uint32_t slice) {
+  if (!s) return SPS_EINVAL;
+  int rc = check_slice(s, slice);
+  if (rc) return rc;
+  s->cur = slice;
+  return SPS_OK;
+}
+
+int sps_merge(sps_sketch* dst, const sps_sketch* const* h_src, uint32_t nsrc, void* stream) {
+  if (!dst || (nsrc && !h_src)) return SPS_EINVAL;
+  const uint16_t* srcs[256];
+  if (nsrc > 256) return SPS_EINVAL;
+  uint32_t cur = dst->cur;
+  for (uint32_t j = 0; j < nsrc; ++j) {
+    if (!h_src[j]) return SPS_EINVAL;
+    if (!same_shape(dst->p, h_src[j]->p)) return SPS_EMISMATCH;
+    srcs[j] = h_src[j]->state;
+    if (h_src[j]->cur > cur) cur = h_src[j]->cur;
+  }
+  if (nsrc) SPS_HIP(sps::launch_merge(dst->state, srcs, nsrc, dst->state_cells, (hipStream_t)stream));
+  dst->cur = cur;
+  return SPS_OK;
+}
+
+int sps_scan_async(sps_sketch* s, uint32_t window, double threshold, sps_result* d_out,
+                   size_t cap, uint32_t* d_info, void* stream) {
+  if (!s || !d_info || (cap && !d_out)) return SPS_EINVAL;
+  if (window < 1 || window > 65534u) return SPS_EINVAL;
+  if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
+  SPS_HIP(sps::launch_scan(s->dev, s->cur, window, threshold, d_out, (uint32_t)cap, d_info,
+                           s->mlp, s->n_cu, (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_scan(sps_sketch* s, uint32_t window, double threshold, sps_result* h_out, size_t cap,
+             size_t* n_out, void* stream) {
+  if (!s || !n_out || (cap && !h_out)) return SPS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = sps_scan_async(s, window, threshold, s->d_sorted, s->p.cand_cap, s->d_info, stream);
+  if (rc) return rc;
+  SPS_HIP(hipMemcpyAsync(s->h_info, s->d_info, SPS_INFO_WORDS * 4, hipMemcpyDeviceToHost, st));
+  SPS_HIP(hipStreamSynchronize(st));
+  const uint32_t kept = s->h_info[SPS_INFO_KEPT];
+  if (s->h_info[SPS_INFO_FLAGS] & 1u) {
+    *n_out = 0;
+    return SPS_ECAPACITY;
+  }
+  *n_out = kept;
+  if (kept > cap) return SPS_ECAPACITY;
+  if (kept) {
+    SPS_HIP(hipMemcpyAsync(h_out, s->d_sorted, (size_t)kept * sizeof(sps_result),
+                           hipMemcpyDeviceToHost, st));
+    SPS_HIP(hipStreamSynchronize(st));
+  }
+  return SPS_OK;
+}
+
+int sps_features(const sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_t window,
+                 uint32_t* d_x, void* stream) {
+  if (!s || (n && (!d_hosts || !d_x))) return SPS_EINVAL;
+  if (window < 1 || window > 32) return SPS_EINVAL;
+  SPS_HIP(sps::launch_features(s->dev, s->cur, window, d_hosts, n, d_x, s->n_cu,
+                               (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_attach_mlp(sps_sketch* s, const float* d_weights, const float* h_feat_lo,
+                   const float* h_feat_hi, double max_card) {
+  if (!s) return SPS_EINVAL;
+  if (!d_weights) {
+    s->mlp.w = nullptr;
+    return SPS_OK;
+  }
+  if (!h_feat_lo || !h_feat_hi || !(max_card > 1.0)) return SPS_EINVAL;
+  s->mlp.w = d_weights;
+  for (int i = 0; i < SPS_MLP_IN; ++i) {
+    s->mlp.lo[i] = h_feat_lo[i];
+    s->mlp.hi[i] = h_feat_hi[i];
+  }
+  s->mlp.log_max = (float)log(max_card);
+  return SPS_OK;
+}
+
+int sps_state_bytes(const sps_sketch* s, size_t* bytes) {
+  if (!s || !bytes) return SPS_EINVAL;
+  const Dev& d = s->dev;
+  *bytes = sizeof(Header) + (size_t)s->sre_cells * 2 + (size_t)d.rp * d.row_len * 2;
+  return SPS_OK;
+}
+
+int sps_export(const sps_sketch* s, void* h_buf, size_t bytes, void* stream) {
+  size_t need = 0;
+  if (!h_buf) return SPS_EINVAL;
+  int rc = sps_state_bytes(s, &need);
+  if (rc) return rc;
+  if (bytes < need) return SPS_ECAPACITY;
+  hipStream_t st = (hipStream_t)stream;
+  Header h{};
+  memcpy(h.magic, "SPS1", 4);
+  h.cur = s->cur;
+  h.p = s->p;
+  memcpy(h_buf, &h, sizeof(h));
+  uint8_t* o = static_cast<uint8_t*>(h_buf) + sizeof(Header);
+  const Dev& d = s->dev;
+  SPS_HIP(hipStreamSynchronize(st));
+  SPS_HIP(hipMemcpy(o, d.sre, (size_t)s->sre_cells * 2, hipMemcpyDeviceToHost));
+  o += (size_t)s->sre_cells * 2;
+  SPS_HIP(hipMemcpy2D(o, (size_t)d.row_len * 2, d.slea, (size_t)d.row_stride * 2,
+                      (size_t)d.row_len * 2, d.rp, hipMemcpyDeviceToHost));
+  return SPS_OK;
+}
+
+int sps_import(sps_sketch* s, const void* h_buf, size_t bytes, void* stream) {
+  size_t need = 0;
+  if (!h_buf) return SPS_EINVAL;
+  int rc = sps_state_bytes(s, &need);
+  if (rc) return rc;
+  if (bytes < need) return SPS_ECAPACITY;
+  Header h;
+  memcpy(&h, h_buf, sizeof(h));
+  sps_params want = s->p;
+  if (memcmp(h.magic, "SPS1", 4) != 0) return SPS_EINVAL;
+  h.p.cand_cap = want.cand_cap;
+  h.p.reserved = want.reserved;
+  if (!same_shape(h.p, want) || h.cur > 65534u) return SPS_EMISMATCH;
+  hipStream_t st = (hipStream_t)stream;
+  const Dev& d = s->dev;
+  const uint8_t* o = static_cast<const uint8_t*>(h_buf) + sizeof(Header);
+  SPS_HIP(hipStreamSynchronize(st));
+  SPS_HIP(hipMemcpy(d.sre, o, (size_t)s->sre_cells * 2, hipMemcpyHostToDevice));
+  o += (size_t)s->sre_cells * 2;
+  SPS_HIP(hipMemcpy2D(d.slea, (size_t)d.row_stride * 2, o, (size_t)d.row_len * 2,
+                      (size_t)d.row_len * 2, d.rp, hipMemcpyHostToDevice));
+  s->cur = h.cur;
+  return SPS_OK;
+}
+
+int sps_current_slice(const sps_sketch* s, uint32_t* slice) {
+  if (!s || !slice) return SPS_EINVAL;
+  *slice = s->cur;
+  return SPS_OK;
+}
+
+int sps_derived(const sps_sketch* s, uint32_t* tau, uint32_t* hot_cut, uint64_t* row_len) {
+  if (!s) return SPS_EINVAL;
+  if (tau) *tau = (uint32_t)__builtin_popcount(s->dev.tau_mask);
+  if (hot_cut) *hot_cut = s->dev.hot_cut;
+  if (row_len) *row_len = s->dev.row_len;
+  return SPS_OK;
+}
+
+int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, size_t* size,
+                   void* stream) {
+  if (!s || !size) return SPS_EINVAL;
+  const Dev& d = s->dev;
+  const void* src = nullptr;
+  size_t full = 0;
+  switch (which) {
+    case 0: src = d.hot; full = ((size_t)d.r << d.q) / 8; break;
+    case 1: {
+      Ctrl c;
+      SPS_HIP(hipStreamSynchronize((hipStream_t)stream));
+      SPS_HIP(hipMemcpy(&c, d.ctrl, sizeof(c), hipMemcpyDeviceToHost));
+      const uint32_t n = c.n_cand < d.cand_cap ? c.n_cand : d.cand_cap;
+      src = d.cand;
+      full = (size_t)n * 4;
+      break;
+    }
+    case 2:
+      src = reinterpret_cast<const uint8_t*>(d.ctrl) + offsetof(Ctrl, row_live);
+      full = (size_t)d.rp * 4;
+      break;
+    default: return SPS_EINVAL;
+  }
+  *size = full;
+  if (h_buf && bytes) {
+    SPS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    SPS_HIP(hipMemcpy(h_buf, src, bytes < full ? bytes : full, hipMemcpyDeviceToHost));
+  }
+  return SPS_OK;
+}
+
+int sps_sync(void* stream) {
+  SPS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  SPS_HIP(hipGetLastError());
+  return SPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// sps_internal.h -- device-side view of a sketch, shared by the kernels and the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sps.h"
+
+namespace sps {
+
+constexpr int kMaxRP = 8;      // SLE-array rows supported
+constexpr int kMaxR = 32;      // SRE-array rows supported
+constexpr int kMaxBatch = 64;  // routers per batched launch
+constexpr int kMaxMerge = 32;  // sources per merge launch (more are chained)
+
+// Per-scan counters kept in device memory (one 256-byte block per sketch).
+struct Ctrl {
+  uint32_t row_live[kMaxRP];  // live cells of every SLE-array row (Def. 4 numerators)
+  uint32_t hse_count[2];      // hot SREs found in rows 0 and 1
+  uint32_t n_cand;            // candidates recovered (counts past the capacity)
+  uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
+  uint32_t pad[64 - kMaxRP - 4];
+};
+static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte block");
+
+// Learned-estimator attachment (weights in device memory, bounds by value).
+struct MlpRef {
+  const float* w;         // SPS_MLP_PARAMS floats, or null
+  float lo[SPS_MLP_IN];   // training range of every feature
+  float hi[SPS_MLP_IN];
+  float log_max;          // outputs above log(max cardinality) fall back
+};
+
+// Everything a kernel needs to know about one sketch; passed by value.
+struct Dev {
+  uint16_t* sre;          // [r][2^q][eta]
+  uint16_t* slea;         // [r'][row_stride], cells >= row_len are padding (always 0)
+  uint32_t* hot;          // [r][2^q / 32] hot-SRE bitmap
+  uint32_t* hse;          // [2][2^q] hot-SRE column lists of rows 0 and 1
+  uint32_t* cand;         // [cand_cap] recovered candidates
+  sps_result* kept;       // [cand_cap] kept hosts, unordered
+  Ctrl* ctrl;
+  uint64_t row_len;       // L' = 2^q' delta' + eta' - delta'
+  uint64_t row_stride;    // cells between SLE-array rows (row_len rounded up to 64)
+  uint32_t q, r, delta, eta;
+  uint32_t qp, rp, etap, deltap;
+  uint32_t tau_mask;      // low tau bits; a pair is sampled when H1 has them all clear
+  uint32_t hot_cut;
+  uint32_t anet_side;
+  uint32_t cand_cap;
+  uint32_t seed_h1, seed_h2, seed_h3, seed_rhfg0;
+  uint32_t seed_lh[kMaxRP];
+};
+
+// ---- hashes (the project's specification: fmix32 of the key xor a per-function seed) ----
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Launchers (sps_kernels.hip).
+hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
+                         int blocks, int threads, hipStream_t st);
+
+struct BatchItem {
+  uint16_t* sre;
+  uint16_t* slea;
+  const sps_pkt* pkts;
+  uint64_t n;
+};
+struct BatchTable {
+  BatchItem item[kMaxBatch];
+  uint64_t tile_start[kMaxBatch + 1];  // prefix sums of tiles per router
+};
+hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t m,
+                                 uint32_t tile, uint16_t stamp, int blocks, int threads,
+                                 hipStream_t st);
+hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
+hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
+                        uint64_t cells, hipStream_t st);
+hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
+                       sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
+                       int n_cu, hipStream_t st);
+hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const uint32_t* hosts,
+                           uint64_t n, uint32_t* x, int n_cu, hipStream_t st);
+
+}  // namespace sps

@@ -1,0 +1,520 @@
+// sps_kernels.hip -- gfx950 kernels of the sliding super point sketch (wave64).
+//
+// Ingest (Alg. 3 + Alg. 6), merge (Alg. 2 + Alg. 7), end-of-slice scan (k-weights and hot
+// SREs of Sec. 3.3 / Def. 4, candidate recovery of Alg. 4-5 through Eq. 6-7, union SLE and
+// estimate of Alg. 8 with Eq. 12 and Eq. 9, final filter), and the per-age features.
+// Recorders are u16 stamps (slice of the last write, 0 = never); see include/sps.h.
+#include <hip/hip_runtime.h>
+
+#include "sps_internal.h"
+
+namespace sps {
+
+constexpr int kWave = 64;
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Ingest.  One lane per IP pair: H3(bip) picks the SLE cell, LH_i(aip) the SLE of row i
+// (Alg. 6); when LSB(H1(bip)) >= tau (low tau bits of H1 clear), H2(bip) picks the SRE
+// cell and RHFG[i](aip) the SRE of row i (Alg. 3, Eq. 6 with shift (i-1)*delta).  Every
+// store writes the same stamp, so plain u16 stores are race-free maxima.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__ sre,
+                                            uint16_t* __restrict__ slea, uint32_t src,
+                                            uint32_t dst, uint16_t stamp) {
+  const uint32_t aip = d.anet_side ? src : dst;
+  const uint32_t bip = d.anet_side ? dst : src;
+  const uint32_t z = fmix32(bip ^ d.seed_h3) & (d.etap - 1u);
+  const uint32_t qpmask = (1u << d.qp) - 1u;
+#pragma unroll
+  for (int i = 0; i < kMaxRP; ++i) {
+    if (i < (int)d.rp) {
+      const uint32_t j = fmix32(aip ^ d.seed_lh[i]) & qpmask;
+      slea[(uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z] = stamp;
+    }
+  }
+  const uint32_t h1 = fmix32(bip ^ d.seed_h1);
+  if ((h1 & d.tau_mask) == 0u) {
+    const uint32_t e = fmix32(bip ^ d.seed_h2) & (d.eta - 1u);
+    const uint32_t qmask = (1u << d.q) - 1u;
+    const uint32_t c0 = fmix32(aip ^ d.seed_rhfg0) & qmask;
+    sre[((uint64_t)c0 << __builtin_ctz(d.eta)) + e] = stamp;
+    for (uint32_t i = 1; i < d.r; ++i) {
+      const uint32_t col = ((aip >> ((i - 1u) * d.delta)) ^ c0) & qmask;
+      sre[((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e] = stamp;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ingest(Dev d, const u32x2* __restrict__ pkts,
+                                                uint64_t n, uint16_t stamp) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const u32x2 pk = __builtin_nontemporal_load(&pkts[i]);
+    ingest_pair(d, d.sre, d.slea, pk.x, pk.y, stamp);
+  }
+}
+
+hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
+                         int blocks, int threads, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t need = (n + threads - 1) / threads;
+  if ((uint64_t)blocks > need) blocks = (int)need;
+  hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(threads), 0, st, d,
+                     reinterpret_cast<const u32x2*>(pkts), n, stamp);
+  return hipGetLastError();
+}
+
+// Batched ingest: the packets of m routers (same shape and hashes, separate arrays) are cut
+// into tiles; work items are tiles, so one launch covers uneven batches.  Block b takes
+// tiles b, b + gridDim.x, ...; the router of a tile is found by binary search of the tile
+// prefix sums held in the kernel arguments.
+__global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uint32_t m,
+                                                        uint32_t tile, uint16_t stamp) {
+  const uint64_t total = t.tile_start[m];
+  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    uint32_t lo = 0, hi = m;  // find j with tile_start[j] <= w < tile_start[j+1]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (t.tile_start[mid] <= w) lo = mid; else hi = mid;
+    }
+    const BatchItem it = t.item[lo];
+    const uint64_t first = (w - t.tile_start[lo]) * tile;
+    uint64_t last = first + tile;
+    if (last > it.n) last = it.n;
+    const u32x2* pk2 = reinterpret_cast<const u32x2*>(it.pkts);
+    for (uint64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+      const u32x2 pk = __builtin_nontemporal_load(&pk2[i]);
+      ingest_pair(d, it.sre, it.slea, pk.x, pk.y, stamp);
+    }
+  }
+}
+
+hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t m,
+                                 uint32_t tile, uint16_t stamp, int blocks, int threads,
+                                 hipStream_t st) {
+  const uint64_t total = t.tile_start[m];
+  if (total == 0) return hipSuccess;
+  if ((uint64_t)blocks > total) blocks = (int)total;
+  hipLaunchKernelGGL(k_ingest_batched, dim3(blocks), dim3(threads), 0, st, shape, t, m, tile,
+                     stamp);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Fill with zeros (reset); a kernel rather than a memset so it can sit inside a graph.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fill_zero(u32x4* __restrict__ p, uint64_t nvec) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+    p[i] = z;
+}
+
+hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st) {
+  const uint64_t nvec = bytes / 16;
+  if (nvec == 0) return hipSuccess;
+  uint64_t blocks = (nvec + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st,
+                     reinterpret_cast<u32x4*>(p), nvec);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Merge (Alg. 2, Alg. 7): dst <- cell-wise max(dst, src_0, ...), 8 stamps per 16-byte lane
+// access; the u16 maxima compile to packed v_pk_max_u16.
+// ---------------------------------------------------------------------------------------
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+struct MergeSrcs {
+  const u16x8* p[kMaxMerge];
+};
+
+__global__ void __launch_bounds__(256) k_merge_max(u16x8* __restrict__ dst, MergeSrcs s,
+                                                   uint32_t nsrc, uint64_t nvec) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    u16x8 v = dst[i];
+    for (uint32_t j = 0; j < nsrc; ++j) v = __builtin_elementwise_max(v, s.p[j][i]);
+    dst[i] = v;
+  }
+}
+
+hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
+                        uint64_t cells, hipStream_t st) {
+  const uint64_t nvec = cells / 8;
+  uint64_t blocks = (nvec + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  for (uint32_t b = 0; b < nsrc; b += kMaxMerge) {
+    MergeSrcs s{};
+    const uint32_t k = nsrc - b < (uint32_t)kMaxMerge ? nsrc - b : (uint32_t)kMaxMerge;
+    for (uint32_t j = 0; j < k; ++j) s.p[j] = reinterpret_cast<const u16x8*>(srcs[b + j]);
+    hipLaunchKernelGGL(k_merge_max, dim3((uint32_t)blocks), dim3(256), 0, st,
+                       reinterpret_cast<u16x8*>(dst), s, k, nvec);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------
+// Scan.
+// ---------------------------------------------------------------------------------------
+__global__ void k_scan_reset(Ctrl* c) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
+}
+
+// number of the 8 u16 stamps in v that are >= lo
+__device__ __forceinline__ uint32_t live8(u32x4 v, uint32_t lo) {
+  uint32_t n = 0;
+  n += (v.x & 0xFFFFu) >= lo;
+  n += (v.x >> 16) >= lo;
+  n += (v.y & 0xFFFFu) >= lo;
+  n += (v.y >> 16) >= lo;
+  n += (v.z & 0xFFFFu) >= lo;
+  n += (v.z >> 16) >= lo;
+  n += (v.w & 0xFFFFu) >= lo;
+  n += (v.w >> 16) >= lo;
+  return n;
+}
+
+// Stage 1.  Blocks [0, rp * nb_row) stream the SLE array, one row per block group, and add
+// their live-cell counts to row_live (Def. 4).  The remaining blocks take one SRE per lane:
+// k-weight >= hot cut marks it hot (Sec. 3.3); a wave's 64 verdicts become one ballot word
+// of the hot bitmap, and rows 0 and 1 also append their hot columns to the HSE lists.
+__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t nb_row) {
+  __shared__ uint32_t red[256 / kWave];
+  const uint32_t b = blockIdx.x;
+  const uint32_t slea_blocks = d.rp * nb_row;
+  if (b < slea_blocks) {
+    const uint32_t row = b / nb_row, chunk = b % nb_row;
+    const u32x4* rowp = reinterpret_cast<const u32x4*>(d.slea + (uint64_t)row * d.row_stride);
+    const uint64_t nvec = d.row_stride / 8;
+    const uint64_t step = (uint64_t)nb_row * blockDim.x;
+    uint32_t cnt = 0;
+    for (uint64_t v = (uint64_t)chunk * blockDim.x + threadIdx.x; v < nvec; v += step)
+      cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[w];
+      atomicAdd(&d.ctrl->row_live[row], t);
+    }
+    return;
+  }
+  const uint64_t sre_idx = (uint64_t)(b - slea_blocks) * blockDim.x + threadIdx.x;
+  const uint64_t n_sre = (uint64_t)d.r << d.q;  // multiple of 64 (q >= 6)
+  if (sre_idx - lane_id() >= n_sre) return;     // whole wave out of range
+  const u32x4* cell = reinterpret_cast<const u32x4*>(d.sre + (sre_idx << __builtin_ctz(d.eta)));
+  uint32_t w = 0;
+  for (uint32_t v = 0; v < d.eta / 8; ++v) w += live8(cell[v], lo);
+  const bool hot = w >= d.hot_cut;
+  const uint64_t mask = __ballot(hot);
+  const uint32_t row = (uint32_t)(sre_idx >> d.q);
+  const uint32_t col = (uint32_t)(sre_idx & ((1u << d.q) - 1u));
+  if (lane_id() == 0) {
+    uint32_t* hw = d.hot + (sre_idx >> 5);
+    hw[0] = (uint32_t)mask;
+    hw[1] = (uint32_t)(mask >> 32);
+  }
+  if (row < 2 && mask != 0) {
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(&d.ctrl->hse_count[row], (uint32_t)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (hot) {
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      d.hse[((uint64_t)row << d.q) + base + below] = col;
+    }
+  }
+}
+
+__device__ __forceinline__ bool hot_bit(const uint32_t* __restrict__ hot, uint32_t q,
+                                        uint32_t row, uint32_t col) {
+  const uint64_t bit = ((uint64_t)row << q) + col;
+  return (hot[bit >> 5] >> (bit & 31u)) & 1u;
+}
+
+// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  One lane per pair (he0, he1) of
+// hot SREs of rows 0 and 1: B(1) = he0 ^ he1 gives address bits [0, q).  Row i >= 2 adds the
+// delta bits [(i-2)delta + q, (i-1)delta + q); its q bits B(i) = x >> ((i-1)delta) then
+// overlap B(i-1) by construction, and the tuple survives when SRE he0 ^ B(i) of row i is hot
+// and no bit at or above 32 is set.  The search is depth first over the 2^delta choices per
+// row; the partial address itself is the stack.  A full tuple is kept when RHFG[0] of the
+// address is he0.
+__global__ void __launch_bounds__(256) k_join(Dev d) {
+  const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
+  const uint64_t pairs = (uint64_t)n0 * n1;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint32_t q = d.q, dl = d.delta, r = d.r;
+  const uint32_t qmask = (1u << q) - 1u, dmask = (1u << dl) - 1u;
+  const uint32_t* __restrict__ hot = d.hot;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += stride) {
+    uint32_t a, bb;
+    if (pairs <= 0xFFFFFFFFull) {
+      a = (uint32_t)p / n1;
+      bb = (uint32_t)p - a * n1;
+    } else {
+      a = (uint32_t)(p / n1);
+      bb = (uint32_t)(p - (uint64_t)a * n1);
+    }
+    const uint32_t he0 = d.hse[a];
+    const uint32_t he1 = d.hse[(1ull << q) + bb];
+    uint64_t x = he0 ^ he1;  // bits [0, q)
+    uint32_t i = 2, t = 0;
+    for (;;) {
+      if (t <= dmask) {
+        const uint32_t sh = (i - 2) * dl + q;  // position of this row's new bits
+        const uint64_t xi = x | ((uint64_t)t << sh);
+        bool ok = (xi >> 32) == 0;
+        if (ok) {
+          const uint32_t Bi = (uint32_t)(xi >> ((i - 1) * dl)) & qmask;
+          ok = hot_bit(hot, q, i, he0 ^ Bi);
+        }
+        if (!ok) {
+          ++t;
+        } else if (i + 1 == r) {
+          const uint32_t addr = (uint32_t)xi;
+          if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+            const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+            if (pos < d.cand_cap) d.cand[pos] = addr;
+          }
+          ++t;
+        } else {
+          x = xi;
+          ++i;
+          t = 0;
+        }
+      } else {
+        if (i == 2) break;
+        --i;
+        const uint32_t sh = (i - 2) * dl + q;
+        t = (uint32_t)((x >> sh) & dmask) + 1u;
+        x &= (1ull << sh) - 1ull;
+      }
+    }
+  }
+}
+
+// Union SLE of host x (Alg. 8): cell z keeps the smallest stamp over the r' rows, i.e. the
+// largest distance, so it is live only when live in every row.  Lane l handles cells
+// l, l + 64, ...; counts of live cells per age come from wave ballots, and lane a ends up
+// holding x_a (cells with stamp >= max(1, cur - a)) for a < nfeat.
+__device__ __forceinline__ void usle_counts(const Dev& d, uint32_t x, uint32_t cur, uint32_t lo,
+                                            uint32_t nfeat, uint32_t& live, uint32_t& feat) {
+  uint64_t base[kMaxRP];
+  const uint32_t qpmask = (1u << d.qp) - 1u;
+#pragma unroll
+  for (int i = 0; i < kMaxRP; ++i)
+    base[i] = (uint64_t)i * d.row_stride + (uint64_t)(fmix32(x ^ d.seed_lh[i]) & qpmask) * d.deltap;
+  live = 0;
+  feat = 0;
+  const uint32_t lane = lane_id();
+  for (uint32_t z0 = 0; z0 < d.etap; z0 += kWave) {
+    const uint32_t z = z0 + lane;
+    uint32_t m = 0;
+    if (z < d.etap) {
+      m = 0xFFFFu;
+#pragma unroll
+      for (int i = 0; i < kMaxRP; ++i)
+        if (i < (int)d.rp) {
+          const uint32_t v = d.slea[base[i] + z];
+          m = v < m ? v : m;
+        }
+    }
+    live += (uint32_t)__popcll(__ballot(m >= lo && m != 0u));
+    for (uint32_t a = 0; a < nfeat; ++a) {
+      const uint32_t lo_a = cur > a + 1u ? cur - a : 1u;
+      const uint32_t c = (uint32_t)__popcll(__ballot(m >= lo_a));
+      if (lane == a) feat += c;
+    }
+  }
+}
+
+// Learned estimator (3-layer perceptron 10 -> 64 -> 64 -> 1 with ReLU): features in lanes
+// 0..9 of the wave, hidden unit j in lane j.  Weights are read as float and rounded to
+// bfloat16 (round to nearest even), activations likewise; products accumulate in float.
+__device__ __forceinline__ float to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+__device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
+  const uint32_t lane = lane_id();
+  const float* W1 = w;
+  const float* b1 = W1 + SPS_MLP_HIDDEN * SPS_MLP_IN;
+  const float* W2 = b1 + SPS_MLP_HIDDEN;
+  const float* b2 = W2 + SPS_MLP_HIDDEN * SPS_MLP_HIDDEN;
+  const float* W3 = b2 + SPS_MLP_HIDDEN;
+  const float* b3 = W3 + SPS_MLP_HIDDEN;
+  const float xin = to_bf16(in_lane);
+  float acc = 0.f;
+  for (int k = 0; k < SPS_MLP_IN; ++k)
+    acc += to_bf16(W1[lane * SPS_MLP_IN + k]) * __shfl(xin, k, kWave);
+  float h1 = to_bf16(fmaxf(acc + b1[lane], 0.f));
+  acc = 0.f;
+  for (int k = 0; k < SPS_MLP_HIDDEN; ++k)
+    acc += to_bf16(W2[lane * SPS_MLP_HIDDEN + k]) * __shfl(h1, k, kWave);
+  const float h2 = to_bf16(fmaxf(acc + b2[lane], 0.f));
+  float y = to_bf16(W3[lane]) * h2;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o, kWave);
+  return y + b3[0];
+}
+
+// Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.
+__global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t lo, uint32_t k,
+                                                  double threshold, MlpRef mlp) {
+  const uint32_t n = min(d.ctrl->n_cand, d.cand_cap);
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  const uint32_t lane = lane_id();
+  const bool use_mlp = mlp.w != nullptr && k == SPS_MLP_IN;
+  const uint32_t nfeat = use_mlp ? SPS_MLP_IN : 0u;
+  double P = 1.0;  // product of the row setting factors SF(i, k), rows in order
+  for (uint32_t i = 0; i < d.rp; ++i)
+    P = P * ((double)d.ctrl->row_live[i] / (double)d.row_len);
+  for (uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; c < n; c += waves) {
+    const uint32_t x = __builtin_amdgcn_readfirstlane(d.cand[c]);
+    uint32_t U, feat;
+    usle_counts(d, x, cur, lo, nfeat, U, feat);
+    const double etap = (double)d.etap;
+    double w;
+    uint32_t flags = 0;
+    if (P >= 1.0)
+      w = (double)U;
+    else
+      w = ((double)U - etap * P) / (1.0 - P);
+    if (w < 0.0) {
+      w = 0.0;
+      flags |= SPS_F_CLAMPLOW;
+    }
+    if (w > etap - 1.0) {
+      w = etap - 1.0;
+      flags |= SPS_F_SATURATED;
+    }
+    double est = -etap * log1p(-w / etap);
+    if (use_mlp) {
+      // use the network only inside its training range and while some age is unsaturated
+      const float f = lane < SPS_MLP_IN ? (float)feat / (float)d.etap : 0.f;
+      const bool in_range = lane >= SPS_MLP_IN || (f >= mlp.lo[lane] && f <= mlp.hi[lane]);
+      const bool all_in = __ballot(!in_range) == 0;
+      const bool informative = __shfl(feat, 0, kWave) < d.etap - 1u;
+      const float y = mlp_forward_wave(mlp.w, f);
+      if (all_in && informative && y >= 0.f && y <= mlp.log_max) {
+        est = (double)expf(y);
+        flags |= SPS_F_MLP;
+      } else {
+        flags |= SPS_F_LC_FALLBACK;
+      }
+    }
+    if (fabs(est - threshold) <= 1e-9 * threshold) flags |= SPS_F_NEAR;
+    if (lane == 0 && est >= threshold) {
+      const uint32_t pos = atomicAdd(&d.ctrl->n_kept, 1u);
+      if (pos < d.cand_cap) {
+        sps_result res;
+        res.host = x;
+        res.live = U;
+        res.flags = flags;
+        res.pad = 0;
+        res.estimate = est;
+        d.kept[pos] = res;
+      }
+    }
+  }
+}
+
+// Stage 4: order the kept hosts ascending.  Hosts are distinct, so a host's rank is the
+// number of smaller kept hosts; every lane counts for one host over LDS tiles of the list.
+__global__ void __launch_bounds__(256) k_rank_sort(Dev d, sps_result* __restrict__ out,
+                                                   uint32_t cap, uint32_t* __restrict__ info) {
+  __shared__ uint32_t tile[1024];
+  const uint32_t n = min(d.ctrl->n_kept, d.cand_cap);
+  const uint32_t gsz = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gsz) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t h = i < n ? d.kept[i].host : 0u;
+    uint32_t rank = 0;
+    for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < 1024 && t0 + j < n; j += blockDim.x)
+        tile[j] = d.kept[t0 + j].host;
+      __syncthreads();
+      const uint32_t m = n - t0 < 1024u ? n - t0 : 1024u;
+      for (uint32_t j = 0; j < m; ++j) rank += tile[j] < h;
+    }
+    if (i < n && rank < cap) out[rank] = d.kept[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && info) {
+    const Ctrl* c = d.ctrl;
+    info[SPS_INFO_KEPT] = c->n_kept;
+    info[SPS_INFO_CAND] = c->n_cand;
+    info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
+    info[SPS_INFO_HSE0] = c->hse_count[0];
+    info[SPS_INFO_HSE1] = c->hse_count[1];
+    info[5] = 0;
+    info[6] = 0;
+    info[7] = 0;
+  }
+}
+
+hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
+                       sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
+                       int n_cu, hipStream_t st) {
+  const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
+  hipLaunchKernelGGL(k_scan_reset, dim3(1), dim3(64), 0, st, d.ctrl);
+  // SLE rows: enough blocks per row that every CU streams, at least 8 vectors per lane
+  const uint64_t nvec_row = d.row_stride / 8;
+  uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
+  const uint64_t want = ((uint64_t)n_cu * 8 + d.rp - 1) / d.rp;
+  if (nb_row > want) nb_row = want;
+  if (nb_row < 1) nb_row = 1;
+  const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
+  hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row + sre_blocks)), dim3(256), 0,
+                     st, d, lo, (uint32_t)nb_row);
+  hipLaunchKernelGGL(k_join, dim3(n_cu * 4), dim3(256), 0, st, d);
+  hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
+                     threshold, mlp);
+  hipLaunchKernelGGL(k_rank_sort, dim3(n_cu), dim3(256), 0, st, d, out, cap, info);
+  return hipGetLastError();
+}
+
+// Features only: per-age cumulative union-SLE live counts of given hosts.
+__global__ void __launch_bounds__(256) k_features(Dev d, uint32_t cur, uint32_t k,
+                                                  const uint32_t* __restrict__ hosts,
+                                                  uint64_t n, uint32_t* __restrict__ x) {
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  const uint32_t lo = cur >= k ? cur - k + 1 : 1u;
+  for (uint64_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; c < n; c += waves) {
+    const uint32_t h = __builtin_amdgcn_readfirstlane(hosts[c]);
+    uint32_t U, feat;
+    usle_counts(d, h, cur, lo, k, U, feat);
+    if (lane_id() < k) x[c * k + lane_id()] = feat;
+  }
+}
+
+hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const uint32_t* hosts,
+                           uint64_t n, uint32_t* x, int n_cu, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 3) / 4;
+  if (blocks > (uint64_t)n_cu * 8) blocks = (uint64_t)n_cu * 8;
+  hipLaunchKernelGGL(k_features, dim3((uint32_t)blocks), dim3(256), 0, st, d, cur, window,
+                     hosts, n, x);
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,331 @@
+"""Thin ctypes binding of the sliding super point sketch library (include/sps.h).
+
+Functions carry the C names and only marshal arguments: torch CUDA tensors become device
+pointers, ``torch.cuda`` streams become hipStream_t handles, numpy arrays hold host data.
+Every step of the method runs in the HIP kernels of ``libsps.so``; if the library is not
+built this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsps.so")
+
+SPS_OK, SPS_EINVAL, SPS_ESLICE, SPS_EMISMATCH = 0, -1, -2, -3
+SPS_ENOMEM, SPS_ECAPACITY, SPS_EHIP, SPS_EBUDGET = -4, -5, -6, -7
+F_SATURATED, F_LC_FALLBACK, F_MLP, F_NEAR, F_CLAMPLOW = 1, 2, 4, 8, 16
+INFO_KEPT, INFO_CAND, INFO_FLAGS, INFO_HSE0, INFO_HSE1, INFO_WORDS = 0, 1, 2, 3, 4, 8
+MLP_IN, MLP_HIDDEN = 10, 64
+MLP_PARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+HEADER_BYTES = 64
+
+EXPORTS = [
+    "sps_sketch_bytes", "sps_create", "sps_destroy", "sps_reset", "sps_ingest",
+    "sps_ingest_batched", "sps_advance", "sps_merge", "sps_scan", "sps_scan_async",
+    "sps_features", "sps_attach_mlp", "sps_state_bytes", "sps_export", "sps_import",
+    "sps_current_slice", "sps_derived", "sps_debug_copy", "sps_sync", "sps_strerror",
+]
+
+
+class SpsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class sps_params(C.Structure):
+    _fields_ = [("q", C.c_uint32), ("r", C.c_uint32), ("delta", C.c_uint32), ("eta", C.c_uint32),
+                ("qp", C.c_uint32), ("rp", C.c_uint32), ("etap", C.c_uint32),
+                ("deltap", C.c_uint32), ("theta", C.c_uint32), ("anet_side", C.c_uint32),
+                ("seed", C.c_uint64), ("cand_cap", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+RESULT_DTYPE = np.dtype([("host", "<u4"), ("live", "<u4"), ("flags", "<u4"), ("pad", "<u4"),
+                         ("estimate", "<f8")])
+assert RESULT_DTYPE.itemsize == 24
+
+_lib = None
+
+
+def lib():
+    """Load libsps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, u32, u64, sz, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t, C.c_int
+        P = C.POINTER
+        sig = {
+            "sps_sketch_bytes": [P(sps_params), P(sz)],
+            "sps_create": [P(sps_params), vp, sz, P(vp)],
+            "sps_destroy": [vp],
+            "sps_reset": [vp, vp],
+            "sps_ingest": [vp, vp, sz, u32, vp],
+            "sps_ingest_batched": [P(vp), P(vp), P(sz), u32, u32, vp],
+            "sps_advance": [vp, u32],
+            "sps_merge": [vp, P(vp), u32, vp],
+            "sps_scan": [vp, u32, C.c_double, vp, sz, P(sz), vp],
+            "sps_scan_async": [vp, u32, C.c_double, vp, sz, vp, vp],
+            "sps_features": [vp, vp, sz, u32, vp, vp],
+            "sps_attach_mlp": [vp, vp, vp, vp, C.c_double],
+            "sps_state_bytes": [vp, P(sz)],
+            "sps_export": [vp, vp, sz, vp],
+            "sps_import": [vp, vp, sz, vp],
+            "sps_current_slice": [vp, P(u32)],
+            "sps_derived": [vp, P(u32), P(u32), P(u64)],
+            "sps_debug_copy": [vp, i32, vp, sz, P(sz), vp],
+            "sps_sync": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.sps_strerror.argtypes = [i32]
+        L.sps_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().sps_strerror(code).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != SPS_OK:
+        raise SpsError(rc, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t: torch.Tensor):
+    assert t.is_cuda and t.is_contiguous(), "device tensor expected"
+    return C.c_void_p(t.data_ptr())
+
+
+def make_params(d: dict) -> sps_params:
+    return sps_params(**{k: int(d.get(k, 0)) for k, _ in sps_params._fields_})
+
+
+# ---------------------------------------------------------------- C functions, same names
+def sps_sketch_bytes(params: dict) -> int:
+    n = C.c_size_t(0)
+    p = make_params(params)
+    _check(lib().sps_sketch_bytes(C.byref(p), C.byref(n)), "sps_sketch_bytes")
+    return n.value
+
+
+def sps_create(params: dict, dev_mem: torch.Tensor | None = None):
+    p = make_params(params)
+    h = C.c_void_p(0)
+    if dev_mem is None:
+        rc = lib().sps_create(C.byref(p), None, 0, C.byref(h))
+    else:
+        rc = lib().sps_create(C.byref(p), _dptr(dev_mem), dev_mem.numel() * dev_mem.element_size(),
+                              C.byref(h))
+    _check(rc, "sps_create")
+    return h
+
+
+def sps_destroy(h):
+    _check(lib().sps_destroy(h), "sps_destroy")
+
+
+def sps_reset(h, stream=None):
+    _check(lib().sps_reset(h, _stream(stream)), "sps_reset")
+
+
+def sps_ingest(h, pkts: torch.Tensor, slice_: int, stream=None):
+    """pkts: (n, 2) 32-bit device tensor of (src, dst) pairs."""
+    n = pkts.shape[0]
+    assert n == 0 or (pkts.dim() == 2 and pkts.shape[1] == 2 and pkts.element_size() == 4)
+    ptr = _dptr(pkts) if n else None
+    _check(lib().sps_ingest(h, ptr, n, slice_, _stream(stream)), "sps_ingest")
+
+
+def sps_ingest_batched(hs, pkts_list, slice_: int, stream=None):
+    m = len(hs)
+    harr = (C.c_void_p * m)(*[h.value for h in hs])
+    parr = (C.c_void_p * m)(*[(p.data_ptr() if p.shape[0] else 0) for p in pkts_list])
+    narr = (C.c_size_t * m)(*[p.shape[0] for p in pkts_list])
+    for p in pkts_list:
+        assert p.shape[0] == 0 or (p.is_cuda and p.is_contiguous() and p.element_size() == 4)
+    _check(lib().sps_ingest_batched(harr, parr, narr, m, slice_, _stream(stream)),
+           "sps_ingest_batched")
+
+
+def sps_advance(h, slice_: int):
+    _check(lib().sps_advance(h, slice_), "sps_advance")
+
+
+def sps_merge(dst, srcs, stream=None):
+    arr = (C.c_void_p * max(1, len(srcs)))(*[s.value for s in srcs])
+    _check(lib().sps_merge(dst, arr, len(srcs), _stream(stream)), "sps_merge")
+
+
+def sps_scan(h, window: int, threshold: float, cap: int = 1 << 16, stream=None) -> np.ndarray:
+    out = np.zeros(cap, dtype=RESULT_DTYPE)
+    n = C.c_size_t(0)
+    rc = lib().sps_scan(h, window, threshold, out.ctypes.data_as(C.c_void_p), cap, C.byref(n),
+                        _stream(stream))
+    if rc == SPS_ECAPACITY:
+        raise SpsError(rc, f"sps_scan (required {n.value})")
+    _check(rc, "sps_scan")
+    return out[: n.value].copy()
+
+
+def sps_scan_async(h, window: int, threshold: float, d_out: torch.Tensor, cap: int,
+                   d_info: torch.Tensor, stream=None):
+    """d_out: device buffer of >= cap * 24 bytes; d_info: device buffer of >= 8 x 4 bytes."""
+    assert d_out.numel() * d_out.element_size() >= cap * 24
+    assert d_info.numel() * d_info.element_size() >= INFO_WORDS * 4
+    _check(lib().sps_scan_async(h, window, threshold, _dptr(d_out), cap, _dptr(d_info),
+                                _stream(stream)), "sps_scan_async")
+
+
+def sps_features(h, d_hosts: torch.Tensor, window: int, d_x: torch.Tensor, stream=None):
+    n = d_hosts.numel()
+    assert d_x.numel() >= n * window and d_x.element_size() == 4 and d_hosts.element_size() == 4
+    _check(lib().sps_features(h, _dptr(d_hosts) if n else None, n, window,
+                              _dptr(d_x) if n else None, _stream(stream)), "sps_features")
+
+
+def sps_attach_mlp(h, d_weights: torch.Tensor | None, feat_lo=None, feat_hi=None,
+                   max_card: float = 1e6):
+    if d_weights is None:
+        _check(lib().sps_attach_mlp(h, None, None, None, 0.0), "sps_attach_mlp")
+        return
+    assert d_weights.dtype == torch.float32 and d_weights.numel() == MLP_PARAMS
+    lo = np.ascontiguousarray(feat_lo, dtype=np.float32)
+    hi = np.ascontiguousarray(feat_hi, dtype=np.float32)
+    _check(lib().sps_attach_mlp(h, _dptr(d_weights), lo.ctypes.data_as(C.c_void_p),
+                                hi.ctypes.data_as(C.c_void_p), max_card), "sps_attach_mlp")
+
+
+def sps_state_bytes(h) -> int:
+    n = C.c_size_t(0)
+    _check(lib().sps_state_bytes(h, C.byref(n)), "sps_state_bytes")
+    return n.value
+
+
+def sps_export(h, stream=None) -> np.ndarray:
+    buf = np.zeros(sps_state_bytes(h), dtype=np.uint8)
+    _check(lib().sps_export(h, buf.ctypes.data_as(C.c_void_p), buf.nbytes, _stream(stream)),
+           "sps_export")
+    return buf
+
+
+def sps_import(h, buf: np.ndarray, stream=None):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(lib().sps_import(h, buf.ctypes.data_as(C.c_void_p), buf.nbytes, _stream(stream)),
+           "sps_import")
+
+
+def sps_current_slice(h) -> int:
+    v = C.c_uint32(0)
+    _check(lib().sps_current_slice(h, C.byref(v)), "sps_current_slice")
+    return v.value
+
+
+def sps_derived(h):
+    tau, cut, rl = C.c_uint32(0), C.c_uint32(0), C.c_uint64(0)
+    _check(lib().sps_derived(h, C.byref(tau), C.byref(cut), C.byref(rl)), "sps_derived")
+    return tau.value, cut.value, rl.value
+
+
+def sps_debug_copy(h, which: int, stream=None) -> np.ndarray:
+    size = C.c_size_t(0)
+    _check(lib().sps_debug_copy(h, which, None, 0, C.byref(size), _stream(stream)),
+           "sps_debug_copy")
+    buf = np.zeros(size.value, dtype=np.uint8)
+    if size.value:
+        _check(lib().sps_debug_copy(h, which, buf.ctypes.data_as(C.c_void_p), buf.nbytes,
+                                    C.byref(size), _stream(stream)), "sps_debug_copy")
+    return buf
+
+
+def sps_sync(stream=None):
+    _check(lib().sps_sync(_stream(stream)), "sps_sync")
+
+
+def sps_strerror(code: int) -> str:
+    return strerror(code)
+
+
+# ---------------------------------------------------------------- convenience owner
+class Sketch:
+    """Owns a sketch and the torch device block it lives in."""
+
+    def __init__(self, params: dict, device: str = "cuda"):
+        self.params = dict(params)
+        self.nbytes = sps_sketch_bytes(params)
+        self.mem = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.h = sps_create(params, self.mem)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            sps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # thin forwards
+    def reset(self, stream=None):
+        sps_reset(self.h, stream)
+
+    def ingest(self, pkts, slice_, stream=None):
+        sps_ingest(self.h, pkts, slice_, stream)
+
+    def advance(self, slice_):
+        sps_advance(self.h, slice_)
+
+    def merge(self, srcs, stream=None):
+        sps_merge(self.h, [s.h for s in srcs], stream)
+
+    def scan(self, window, threshold, cap=1 << 16, stream=None):
+        return sps_scan(self.h, window, threshold, cap, stream)
+
+    def features(self, hosts: torch.Tensor, window: int, stream=None) -> torch.Tensor:
+        x = torch.zeros((hosts.numel(), window), dtype=torch.int32, device=hosts.device)
+        sps_features(self.h, hosts, window, x, stream)
+        return x
+
+    @property
+    def cur(self):
+        return sps_current_slice(self.h)
+
+    def derived(self):
+        return sps_derived(self.h)
+
+    def export(self, stream=None) -> np.ndarray:
+        return sps_export(self.h, stream)
+
+    def import_(self, buf, stream=None):
+        sps_import(self.h, buf, stream)
+
+    def state(self, stream=None):
+        """(SRE u16 (r, 2^q, eta), SLE array u16 (r', L')) from a bit-exact dump."""
+        return split_dump(self.export(stream), self.params)
+
+
+def split_dump(buf: np.ndarray, params: dict):
+    p = params
+    n_sre = (p["r"] << p["q"]) * p["eta"]
+    row_len = (1 << p["qp"]) * p["deltap"] + p["etap"] - p["deltap"]
+    body = buf[HEADER_BYTES:].view(np.uint16)
+    sre = body[:n_sre].reshape(p["r"], 1 << p["q"], p["eta"])
+    slea = body[n_sre:n_sre + p["rp"] * row_len].reshape(p["rp"], row_len)
+    return sre, slea

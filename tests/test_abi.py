@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every symbol include/sps.h declares; host-only entry
+points (parameter validation, sizes, error strings) work without a GPU."""
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "sps.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(sps_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1805_09246_amd import sps
+    if not os.path.exists(sps.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return sps
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 20
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTS) == names
+
+
+def test_no_cpu_fallback_in_binding():
+    src = open(os.path.join(ROOT, "paper_1805_09246_amd", "sps.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src
+    for f in os.listdir(os.path.join(ROOT, "paper_1805_09246_amd", "csrc")):
+        assert "oracle" not in open(os.path.join(ROOT, "paper_1805_09246_amd", "csrc", f)).read()
+
+
+def test_sketch_bytes_and_validation(L):
+    from synth.configs import C1_PARAMS, C2_PARAMS
+    n1 = L.sps_sketch_bytes(C1_PARAMS)
+    # SRE 6*4096*8*2 + SLE 5*4096*1024*2 + workspace
+    assert n1 > 6 * 4096 * 16 + 5 * 4096 * 1024 * 2
+    assert L.sps_sketch_bytes(C2_PARAMS) > 640 * 2 ** 20
+    bad = [
+        dict(C1_PARAMS, r=5),            # (r-2)*delta + q = 27 < 32
+        dict(C1_PARAMS, eta=6),
+        dict(C1_PARAMS, etap=1000),
+        dict(C1_PARAMS, deltap=2048),    # delta' > eta'
+        dict(C1_PARAMS, rp=9),
+        dict(C1_PARAMS, q=5),
+        dict(C1_PARAMS, theta=0),
+        dict(C1_PARAMS, anet_side=2),
+        dict(C1_PARAMS, delta=12),       # delta >= q
+    ]
+    for p in bad:
+        with pytest.raises(L.SpsError) as e:
+            L.sps_sketch_bytes(p)
+        assert e.value.code == L.SPS_EINVAL
+    assert L.sps_sketch_bytes(dict(C1_PARAMS, deltap=16)) < n1
+
+
+def test_strerror(L):
+    for code in range(0, -8, -1):
+        assert len(L.strerror(code)) >= 2
+    assert L.strerror(-99) == "unknown error"

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Sketch state, hot SREs, row live counts and candidate lists must be bit-exact; estimates
+within 4 ulp (fp64, device log1p vs glibc); reported hosts, |USLE|^k and flags exact.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import (assert_estimates_close, assert_scan_equal, assert_state_equal,
+                      dev_pkts, gpu_candidates)
+from paper_1805_09246_amd import sps
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(q=12, r=6, delta=5, eta=8, qp=8, rp=3, etap=64, deltap=16, theta=64, anet_side=0,
+             seed=0xC0FFEE)
+
+
+def _rand_pkts(rng, n, hosts=300, zipf=1.3):
+    dst = (rng.zipf(zipf, n).astype(np.uint64) % hosts * 2654435761 + 12345).astype(np.uint32)
+    src = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    return np.stack([src, dst], 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    torch.cuda.set_device(0)
+    print(f"[gpu] {torch.cuda.get_device_name(0)}", flush=True)
+    yield
+    torch.cuda.synchronize()
+
+
+def test_c1_full_stream(c1_stream):
+    """Config 1 (2^20 packets, 10 slices, window 5, threshold 1024): state after every slice
+    and the scan after every full window."""
+    from synth.configs import C1_PARAMS, C1_THRESHOLD, C1_WINDOW
+    g = sps.Sketch(C1_PARAMS)
+    o = oracle.OracleSketch(C1_PARAMS)
+    assert g.derived() == (o.tau, o.hot_cut, o.row_len)
+    for s in range(1, 11):
+        p = c1_stream.slice_pkts(s)
+        g.ingest(dev_pkts(p), s)
+        assert o.ingest(p, s) == 0
+        assert_state_equal(g, o, f"slice {s}")
+        if s >= C1_WINDOW:
+            got = assert_scan_equal(g, o, C1_WINDOW, C1_THRESHOLD, f"scan at slice {s}")
+            print(f"[c1] slice {s}: {len(got)} hosts reported", flush=True)
+    g.close()
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 257, 4097, 100003])
+def test_ragged_batch_sizes(n):
+    rng = np.random.default_rng(n + 1)
+    g, o = sps.Sketch(SMALL), oracle.OracleSketch(SMALL)
+    for s in (1, 2):
+        p = _rand_pkts(rng, n)
+        g.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+    assert_state_equal(g, o, f"n={n}")
+    assert_scan_equal(g, o, 2, 40.0, f"n={n}")
+
+
+SHAPES = [
+    dict(SMALL),                                           # shared SLE cells (delta' < eta')
+    dict(SMALL, deltap=64),                                # no sharing
+    dict(SMALL, anet_side=1),                              # aip = src
+    dict(SMALL, eta=16, theta=128),                        # 16-cell SREs, hot cut 5
+    dict(SMALL, rp=1, deltap=1),                           # one SLE row, densest sharing
+    dict(SMALL, q=10, r=7, delta=5),                       # 35-bit coverage
+    dict(SMALL, q=14, r=11, delta=2, qp=10, rp=8),         # config-2 SRE shape, 8 SLE rows
+    dict(SMALL, etap=2048, deltap=2048, qp=6, theta=16),   # eta' > 1024, tau = 1
+]
+
+
+@pytest.mark.parametrize("params", SHAPES, ids=lambda p: f"q{p['q']}r{p['r']}e{p['eta']}"
+                         f"rp{p['rp']}ep{p['etap']}dp{p['deltap']}s{p['anet_side']}")
+def test_shapes(params):
+    rng = np.random.default_rng(params["q"] * 7 + params["rp"])
+    g, o = sps.Sketch(params), oracle.OracleSketch(params)
+    for s in (1, 2, 3, 5, 6):
+        p = _rand_pkts(rng, 20000, hosts=200, zipf=1.2)
+        g.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+    assert_state_equal(g, o)
+    for k in (1, 3, 6, 100):
+        assert_scan_equal(g, o, k, 30.0, f"k={k}")
+
+
+def test_merge_parity_and_union():
+    rng = np.random.default_rng(3)
+    n_r = 4
+    gs = [sps.Sketch(SMALL) for _ in range(n_r)]
+    os_ = [oracle.OracleSketch(SMALL) for _ in range(n_r)]
+    whole = sps.Sketch(SMALL)
+    for s in (1, 2, 4):
+        p = _rand_pkts(rng, 30000)
+        who = rng.integers(0, n_r, len(p))
+        whole.ingest(dev_pkts(p), s)
+        for j in range(n_r):
+            gs[j].ingest(dev_pkts(p[who == j]), s)
+            os_[j].ingest(p[who == j], s)
+    gm, om = sps.Sketch(SMALL), oracle.OracleSketch(SMALL)
+    gm.merge(gs)
+    om.merge(os_)
+    assert_state_equal(gm, om, "merged")
+    # union: merging the routers equals one sketch fed everything
+    ws, wl = whole.state()
+    ms, ml = gm.state()
+    assert np.array_equal(ws, ms) and np.array_equal(wl, ml)
+    assert_scan_equal(gm, om, 3, 40.0, "merged scan")
+    # accumulate into a router that is also a source
+    gs[0].merge(gs[1:] + [gs[0]])
+    s0, l0 = gs[0].state()
+    assert np.array_equal(s0, ms) and np.array_equal(l0, ml)
+
+
+def test_batched_ingest_parity():
+    rng = np.random.default_rng(5)
+    sizes = [0, 1, 5000, 70001, 300, 4096, 4097]
+    gs = [sps.Sketch(SMALL) for _ in sizes]
+    os_ = [oracle.OracleSketch(SMALL) for _ in sizes]
+    for s in (1, 2, 3):
+        ps = [_rand_pkts(rng, n) for n in sizes]
+        sps.sps_ingest_batched([g.h for g in gs], [dev_pkts(p) for p in ps], s)
+        for o, p in zip(os_, ps):
+            o.ingest(p, s)
+    for j, (g, o) in enumerate(zip(gs, os_)):
+        assert_state_equal(g, o, f"router {j}")
+
+
+def test_export_import_reset_resume():
+    rng = np.random.default_rng(7)
+    a, o = sps.Sketch(SMALL), oracle.OracleSketch(SMALL)
+    pk = [_rand_pkts(rng, 8000) for _ in range(4)]
+    for s in (1, 2):
+        a.ingest(dev_pkts(pk[s - 1]), s)
+        o.ingest(pk[s - 1], s)
+    dump = a.export()
+    b = sps.Sketch(SMALL)
+    b.import_(dump)
+    assert b.cur == 2
+    for s in (3, 4):   # resume both
+        a.ingest(dev_pkts(pk[s - 1]), s)
+        b.ingest(dev_pkts(pk[s - 1]), s)
+        o.ingest(pk[s - 1], s)
+    assert_state_equal(b, o, "resumed")
+    assert np.array_equal(a.export(), b.export())
+    a.reset()
+    sre, slea = a.state()
+    assert a.cur == 0 and not sre.any() and not slea.any()
+    other = sps.Sketch(dict(SMALL, seed=1))
+    with pytest.raises(sps.SpsError) as e:
+        other.import_(dump)
+    assert e.value.code == sps.SPS_EMISMATCH
+
+
+def test_features_parity(c1_stream):
+    from synth.configs import C1_PARAMS
+    g, o = sps.Sketch(C1_PARAMS), oracle.OracleSketch(C1_PARAMS)
+    for s in range(1, 8):
+        p = c1_stream.slice_pkts(s)
+        g.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+    rng = np.random.default_rng(0)
+    hosts = np.concatenate([c1_stream.planted_hosts,
+                            rng.integers(0, 1 << 32, 500, dtype=np.uint64).astype(np.uint32),
+                            c1_stream.pkts[:300, 1]])
+    hd = torch.from_numpy(hosts.view(np.int32)).cuda()
+    for k in (1, 5, 10, 32):
+        x = g.features(hd, k).cpu().numpy().view(np.uint32)
+        assert np.array_equal(x, o.features(k, hosts)), f"k={k}"
+    with pytest.raises(sps.SpsError):
+        g.features(hd, 33)
+
+
+def test_error_paths():
+    rng = np.random.default_rng(9)
+    g = sps.Sketch(SMALL)
+    p = dev_pkts(_rand_pkts(rng, 100))
+    for bad in (0, 65535):
+        with pytest.raises(sps.SpsError) as e:
+            g.ingest(p, bad)
+        assert e.value.code == sps.SPS_ESLICE
+    g.ingest(p, 5)
+    with pytest.raises(sps.SpsError) as e:
+        g.ingest(p, 4)
+    assert e.value.code == sps.SPS_ESLICE
+    with pytest.raises(sps.SpsError) as e:
+        g.merge([sps.Sketch(dict(SMALL, seed=2))])
+    assert e.value.code == sps.SPS_EMISMATCH
+    with pytest.raises(sps.SpsError) as e:
+        sps.sps_ingest_batched([g.h, sps.Sketch(dict(SMALL, seed=2)).h], [p, p], 6)
+    assert e.value.code == sps.SPS_EMISMATCH
+    with pytest.raises(sps.SpsError) as e:
+        g.scan(0, 10.0)
+    assert e.value.code == sps.SPS_EINVAL
+    g.advance(7)
+    assert g.cur == 7
+    # result capacity: required count reported, retry gives the same list
+    many = dev_pkts(_rand_pkts(rng, 200000, hosts=50, zipf=1.01))
+    g.ingest(many, 8)
+    full = g.scan(2, 1.0)
+    assert len(full) > 2
+    with pytest.raises(sps.SpsError) as e:
+        g.scan(2, 1.0, cap=2)
+    assert e.value.code == sps.SPS_ECAPACITY and f"required {len(full)}" in str(e.value)
+    again = g.scan(2, 1.0)
+    assert np.array_equal(again, full)
+
+
+def test_candidate_overflow():
+    rng = np.random.default_rng(10)
+    g = sps.Sketch(dict(SMALL, cand_cap=4))
+    g.ingest(dev_pkts(_rand_pkts(rng, 200000, hosts=50, zipf=1.01)), 1)
+    with pytest.raises(sps.SpsError) as e:
+        g.scan(1, 1.0)
+    assert e.value.code == sps.SPS_ECAPACITY
+
+
+def test_scan_async_matches_sync(c1_stream):
+    from synth.configs import C1_PARAMS
+    g = sps.Sketch(C1_PARAMS)
+    for s in range(1, 6):
+        g.ingest(dev_pkts(c1_stream.slice_pkts(s)), s)
+    sync = g.scan(5, 1024.0)
+    out = torch.zeros(4096 * 24, dtype=torch.uint8, device="cuda")
+    info = torch.zeros(8, dtype=torch.int32, device="cuda")
+    sps.sps_scan_async(g.h, 5, 1024.0, out, 4096, info)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    res = out.cpu().numpy().view(sps.RESULT_DTYPE)[: inf[sps.INFO_KEPT]]
+    assert np.array_equal(res, sync)
+    assert inf[sps.INFO_CAND] >= inf[sps.INFO_KEPT] and inf[sps.INFO_FLAGS] == 0
+
+
+def test_launch_geometry_invariance():
+    """Different packet splits and orders give identical state (Sec. 3.3: no sync needed)."""
+    rng = np.random.default_rng(11)
+    p = _rand_pkts(rng, 50000)
+    a, b = sps.Sketch(SMALL), sps.Sketch(SMALL)
+    a.ingest(dev_pkts(p), 1)
+    q = p[rng.permutation(len(p))]
+    for part in np.array_split(q, 7):
+        b.ingest(dev_pkts(part), 1)
+    assert np.array_equal(a.export(), b.export())
+
+
+@pytest.mark.slow
+def test_c2_full_size():
+    """Config 2 at full size (2^26 packets, 60 slices, window 10): whole state after slices
+    10, 35 and 60 and the full scan there."""
+    from synth import make_stream
+    from synth.configs import C2_PARAMS, C2_RECIPE, C2_THRESHOLD, C2_WINDOW
+    st = make_stream(C2_RECIPE)
+    print("[c2] stream generated", flush=True)
+    g, o = sps.Sketch(C2_PARAMS), oracle.OracleSketch(C2_PARAMS)
+    for s in range(1, 61):
+        p = st.slice_pkts(s)
+        g.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+        if s in (10, 35, 60):
+            assert_state_equal(g, o, f"slice {s}")
+            got = assert_scan_equal(g, o, C2_WINDOW, C2_THRESHOLD, f"c2 scan at {s}")
+            print(f"[c2] slice {s}: state equal, {len(got)} hosts", flush=True)
+    g.close()
