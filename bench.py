@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the sliding super point hot path on one MI355X.
+
+Workload (single router at scale): 2^26 synthetic packets over 60 time slices, window 10,
+threshold 1024; SRE array 11 x 16384 x 8 u16, SLE array 5 x 65536 x 1024 u16.  One step is
+the whole job: reset the sketch, ingest each slice's packets (per-packet SRE + SLE stamp
+writes), and after every slice with a full window scan it (row live counts + hot SREs,
+candidate recovery, union-SLE estimates, filter, ordered report) -- 60 ingests, 51 scans.
+All packets are resident in device memory before the timed region starts.
+
+Prints ONE JSON line.  `value` is whole-job packets per second (ingest and scans both
+inside the timed region).  Per-kernel durations come from HIP events the library records
+on the stream each kernel runs on, inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "packets/s ingested (SRE+SLE) + scan ms/slice; p99 latency; learned vs LC rel. error"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1805_09246_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1805_09246_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(stream, params, window, threshold, n_slices_sample=10, n_scans=2):
+    """The oracle timed on the host on a bounded sample: ingest of the first slices, then a
+    few scans; scaled to the whole job's packets/s."""
+    import oracle
+    threads = oracle.default_threads()
+    o = oracle.OracleSketch(params)
+    t0 = time.perf_counter()
+    n_pk = 0
+    for s in range(1, n_slices_sample + 1):
+        p = stream.slice_pkts(s)
+        o.ingest(p, s)
+        n_pk += p.shape[0]
+    t_ing = time.perf_counter() - t0
+    t_scan = []
+    for j in range(n_scans):
+        s = n_slices_sample + j
+        if j:
+            p = stream.slice_pkts(s)
+            t1 = time.perf_counter()
+            o.ingest(p, s)
+            t_ing += time.perf_counter() - t1
+            n_pk += p.shape[0]
+        t1 = time.perf_counter()
+        o.scan(window, threshold, threads=threads)
+        t_scan.append(time.perf_counter() - t1)
+    per_pkt = t_ing / n_pk
+    scan_s = sum(t_scan) / len(t_scan)
+    rec = stream.recipe
+    n_scans_job = rec.n_slices - window + 1
+    job_s = per_pkt * rec.n_packets + scan_s * n_scans_job
+    return {
+        "value": rec.n_packets / job_s,
+        "unit": "packets/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle ingest of slices 1..{n_slices_sample + n_scans - 1} "
+                   f"({n_pk} packets, 1 thread, {t_ing:.2f} s) and {n_scans} scans "
+                   f"(exhaustive candidate search on {threads} threads, "
+                   f"{scan_s:.2f} s each), scaled to {rec.n_packets} packets and "
+                   f"{n_scans_job} scans"),
+        "ingest_pkts_per_s": 1.0 / per_pkt,
+        "scan_ms_per_slice": scan_s * 1e3,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the "
+              f"sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1805_09246_amd import sps
+    from synth import make_stream
+    from synth.configs import C2_PARAMS, C2_RECIPE, C2_THRESHOLD, C2_WINDOW
+
+    torch.cuda.set_device(0)
+    rec, params, K_WIN, THETA = C2_RECIPE, C2_PARAMS, C2_WINDOW, C2_THRESHOLD
+    t0 = time.perf_counter()
+    st = make_stream(rec)
+    log(f"stream generated in {time.perf_counter() - t0:.1f} s")
+    pkts = torch.from_numpy(st.pkts.view(np.int32)).cuda()
+    offs = [int(v) for v in st.slice_off]
+    slices = [pkts[offs[s - 1]:offs[s]] for s in range(1, rec.n_slices + 1)]
+    sk = sps.Sketch(params)
+    n_scans = rec.n_slices - K_WIN + 1
+    cap = 8192
+    res = torch.zeros((n_scans, cap * 24), dtype=torch.uint8, device="cuda")
+    info = torch.zeros((n_scans, 8), dtype=torch.int32, device="cuda")
+
+    def step():
+        sk.reset()
+        for s in range(1, rec.n_slices + 1):
+            sps.sps_ingest(sk.h, slices[s - 1], s)
+            if s >= K_WIN:
+                j = s - K_WIN
+                sps.sps_scan_async(sk.h, K_WIN, THETA, res[j], cap, info[j])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    if (inf[:, sps.INFO_FLAGS] != 0).any():
+        raise RuntimeError("scan buffers overflowed")
+    log(f"warm-up done; hosts reported per scan: {int(inf[:, 0].min())}..{int(inf[:, 0].max())}")
+
+    sps.sps_profile_enable(True)
+    sps.sps_profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = sps.sps_profile_read()
+    sps.sps_profile_enable(False)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    total_pkts = args.steps * rec.n_packets
+    value = total_pkts / elapsed
+    tau, _, row_len = sk.derived()
+    stores_per_pkt = params["rp"] + params["r"] * 2.0 ** -tau
+    ingest_bytes_per_pkt = 8 + 2 * stores_per_pkt
+    stats_bytes = 2 * (params["rp"] * row_len + (params["r"] << params["q"]) * params["eta"]) \
+        + (params["r"] << params["q"]) // 8
+    alg_bytes = {
+        "ingest": rec.n_packets / rec.n_slices * ingest_bytes_per_pkt,
+        "scan_stats": stats_bytes,
+    }
+    stage_ms = {k: {"total_ms": round(v[0], 3), "launches": v[1],
+                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
+                for k, v in prof.items() if v[1]}
+    dominant = max(prof, key=lambda k: prof[k][0])
+    avg_s = prof[dominant][0] / prof[dominant][1] / 1e3
+    kernel_names = {"ingest": "k_ingest", "scan_stats": "k_scan_stats", "join": "k_join",
+                    "estimate": "k_estimate", "sort": "k_rank_sort", "fill": "k_fill_zero"}
+    if dominant in alg_bytes:
+        achieved = alg_bytes[dominant] / avg_s / 1e9
+        traffic = stored_traffic(kernel_names[dominant])
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "traffic": traffic, "kernel": kernel_names[dominant],
+                    "alg_bytes_per_launch": int(alg_bytes[dominant]),
+                    "avg_launch_us": round(avg_s * 1e6, 2)}
+    else:
+        roofline = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "kernel": kernel_names.get(dominant, dominant),
+                    "avg_launch_us": round(avg_s * 1e6, 2)}
+    per_kernel = {}
+    for k, b in alg_bytes.items():
+        if prof[k][1]:
+            a = b / (prof[k][0] / prof[k][1] / 1e3) / 1e9
+            per_kernel[kernel_names[k]] = {"achieved_GBps": round(a, 2),
+                                           "frac_of_8TBps": round(a / PEAK_HBM_GBS, 4),
+                                           "alg_bytes_per_launch": int(b)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": rec.name, "packets": rec.n_packets, "slices": rec.n_slices,
+                   "window": K_WIN, "threshold": THETA,
+                   "sre": f"{params['r']}x{1 << params['q']}x{params['eta']} u16",
+                   "sle": f"{params['rp']}x{1 << params['qp']}x{params['etap']} u16",
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "ingest_pkts_per_s": total_pkts / (prof["ingest"][0] / 1e3),
+        "scan_ms_per_slice": sum(prof[k][0] for k in
+                                 ("scan_reset", "scan_stats", "join", "estimate", "sort"))
+        / (args.steps * n_scans),
+        "stage_ms": stage_ms,
+        "per_kernel_roofline": per_kernel,
+    }
+
+    if not args.no_probes:
+        # measured roofline of the ingest's access pattern (same array size, same stores)
+        probe = torch.zeros(params["rp"] * row_len, dtype=torch.int16, device="cuda")
+        ssum = torch.zeros(1, dtype=torch.int32, device="cuda")
+        n_st = int(rec.n_packets / rec.n_slices * stores_per_pkt)
+        for _ in range(2):
+            sps.sps_probe_scatter(probe, n_st, 1, 1)
+            sps.sps_probe_stream(probe, ssum)
+        torch.cuda.synchronize()
+        sps.sps_profile_enable(True)
+        sps.sps_profile_read()
+        for i in range(10):
+            sps.sps_probe_scatter(probe, n_st, 100 + i, 2)
+        sc = sps.sps_profile_read()["probe"]
+        for i in range(10):
+            sps.sps_probe_stream(probe, ssum)
+        sm = sps.sps_profile_read()["probe"]
+        sps.sps_profile_enable(False)
+        R_s = n_st / (sc[0] / sc[1] / 1e3)
+        BW_s = probe.numel() * 2 / (sm[0] / sm[1] / 1e3)
+        roof_pkts = 1.0 / (8.0 / BW_s + stores_per_pkt / R_s)
+        ing = total_pkts / (prof["ingest"][0] / 1e3)
+        out["roofline_measured"] = {
+            "scatter_stores_per_s": R_s, "stream_GBps": BW_s / 1e9,
+            "ingest_roofline_pkts_per_s": roof_pkts,
+            "ingest_frac_of_measured": ing / roof_pkts,
+            "scan_stats_frac_of_stream": (stats_bytes / (prof["scan_stats"][0] /
+                                                         prof["scan_stats"][1] / 1e3)) / BW_s,
+        }
+        del probe
+
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(st, params, K_WIN, THETA)
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f} s")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

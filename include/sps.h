@@ -119,10 +119,12 @@ int sps_reset(sps_sketch* s, void* stream);
  * (Sec. 3.3: recorders need no synchronization). */
 int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, void* stream);
 
-/* The same for m sketches (routers) at once, in one persistent launch: sketch s[j] ingests
- * the n[j] pairs at d_pkts[j].  h_s, h_pkts, h_n are host arrays of m entries; the
- * pair buffers are device memory.  All sketches must be on the current device; the slice
- * rules of sps_ingest apply to each (checked for all before anything is written). */
+/* The same for m sketches (routers) at once, in one launch per 64 routers: sketch h_s[j]
+ * ingests the h_n[j] pairs at h_pkts[j].  h_s, h_pkts, h_n are host arrays of m entries; the
+ * pair buffers are device memory.  As the paper requires of distributed nodes (Sec. 3.3),
+ * all sketches share parameters and seed (else SPS_EMISMATCH) and live on the current
+ * device; the slice rules of sps_ingest apply to each (checked for all before anything is
+ * written).  Work is cut into tiles of a tuned size so uneven batches share one launch. */
 int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
                        uint32_t m, uint32_t slice, void* stream);
 
@@ -160,17 +162,54 @@ int sps_scan_async(sps_sketch* s, uint32_t window, double threshold, sps_result*
 int sps_features(const sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_t window,
                  uint32_t* d_x, void* stream);
 
-/* Attach a learned estimator to the sketch's scans (NULL detaches).  d_weights: device
- * buffer of SPS_MLP_PARAMS floats in the order W1(64x10), b1, W2(64x64), b2, W3(1x64), b3,
- * caller-owned, read by every later scan.  feat_lo/feat_hi: per-feature bounds of the
- * training range (host arrays of 10 floats, copied); outside them, or when every feature is
- * saturated, or when the output leaves [0, log(max_card)], linear counting is used.
- * Only scans with window 10 use it. */
+/* Estimates of given hosts (no recovery, no filter): for each d_hosts[h] the union SLE,
+ * Eq. 12 and Eq. 9 (or the attached learned estimator) over a window of `window` slices
+ * ending at the current slice, written to d_out[h] in input order.  1 <= window <= 65534. */
+int sps_estimate_hosts(sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_t window,
+                       sps_result* d_out, void* stream);
+
+/* ---- learned cardinality estimator (an addition to the paper's method) --------------------
+ * A 3-layer perceptron maps the per-age union-SLE live counts x_0..x_9 of a host (window 10,
+ * each divided by eta') through 64 and 64 ReLU units to the natural log of its cardinality.
+ * Parameters: SPS_MLP_PARAMS float32 in the order W1 (64 x 10, row-major), b1 (64),
+ * W2 (64 x 64), b2 (64), W3 (1 x 64), b3 (1). */
 #define SPS_MLP_IN 10
 #define SPS_MLP_HIDDEN 64
 #define SPS_MLP_PARAMS (SPS_MLP_HIDDEN * SPS_MLP_IN + SPS_MLP_HIDDEN + SPS_MLP_HIDDEN * SPS_MLP_HIDDEN + SPS_MLP_HIDDEN + SPS_MLP_HIDDEN + 1)
+
+/* Attach a trained network to the sketch's scans and host estimates (d_weights NULL
+ * detaches).  d_weights: caller-owned device buffer, read by every later scan.  The network
+ * replaces linear counting for a host only when its window is 10 slices, |USLE|^k >=
+ * min_live, every feature x_a / eta' lies in [h_feat_lo[a], h_feat_hi[a]] (host arrays of
+ * 10 floats, copied), x_0 < eta' - 1 (some age is unsaturated), and the output lies in
+ * [0, log(max_card)]; otherwise linear counting is kept and SPS_F_LC_FALLBACK is set.
+ * Inference rounds weights and activations to bfloat16 and accumulates in float32. */
 int sps_attach_mlp(sps_sketch* s, const float* d_weights, const float* h_feat_lo,
-                   const float* h_feat_hi, double max_card);
+                   const float* h_feat_hi, uint32_t min_live, double max_card);
+
+/* Bytes of the workspace sps_mlp_grad needs for a batch of n samples. */
+int sps_mlp_work_bytes(size_t n, size_t* bytes);
+
+/* Gradient of the mean squared error of log-cardinality predictions over a batch:
+ * samples d_idx[0..n) (or 0..n when d_idx is NULL) of the feature matrix d_feat (u32,
+ * n_rows x 10 counts, divided by eta' inside) with targets d_target (float, log of the true
+ * cardinality).  Writes SPS_MLP_PARAMS floats to d_grad and the batch loss to d_loss
+ * (may be NULL).  d_work: sps_mlp_work_bytes(n) bytes of device memory.  Deterministic:
+ * partial gradients are summed in a fixed order. */
+int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target,
+                 const uint32_t* d_idx, size_t n, uint32_t etap, void* d_work, float* d_grad,
+                 float* d_loss, void* stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected; step counts from 1) on d_w with moment
+ * buffers d_m, d_v (SPS_MLP_PARAMS floats each). */
+int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32_t step,
+                 float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Batched inference: d_y[s] = predicted log cardinality of feature row s (n rows of 10 u32
+ * counts).  bf16 != 0 uses the scan's precision (bfloat16 weights and activations, float32
+ * accumulation); 0 uses float32 throughout. */
+int sps_mlp_forward(const float* d_w, const uint32_t* d_feat, size_t n, uint32_t etap, int bf16,
+                    float* d_y, void* stream);
 
 /* Bytes of a state dump (header + SRE array + SLE array, dense). */
 int sps_state_bytes(const sps_sketch* s, size_t* bytes);
@@ -191,11 +230,45 @@ int sps_current_slice(const sps_sketch* s, uint32_t* slice);
 int sps_derived(const sps_sketch* s, uint32_t* tau, uint32_t* hot_cut, uint64_t* row_len);
 
 /* Internal scan buffers of the last scan, for inspection: which = 0 hot bitmap
- * (r x 2^q bits as u32 words), 1 candidate list (u32, unordered), 2 SLE row live counts
- * (r' x u64 ... stored as u32).  Copies min(bytes, size) bytes to host memory; *size gets
- * the full size.  Synchronous. */
+ * (r x 2^q bits as u32 words, bit j of word w = SRE 32w + j in row-major order), 1 candidate
+ * list (u32, unordered, at most cand_cap), 2 SLE row live counts (r' x u32).  Copies
+ * min(bytes, size) bytes to host memory h_buf (may be NULL to query); *size gets the full
+ * size.  Synchronous. */
 int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, size_t* size,
                    void* stream);
+
+/* ---- measurement ------------------------------------------------------------------------ */
+/* Stage timing with HIP events on the stream each kernel is launched on.  While enabled
+ * (process-wide), every library kernel launch is bracketed by a pair of events; reading
+ * synchronizes on the recorded events and returns, per stage, the summed milliseconds and
+ * the number of launches since the last read, then clears.  Not for use under stream
+ * capture.  h_ms / h_launches: host arrays of nstages entries (stages beyond
+ * SPS_NSTAGES are zeroed). */
+#define SPS_STAGE_INGEST 0
+#define SPS_STAGE_INGEST_BATCHED 1
+#define SPS_STAGE_MERGE 2
+#define SPS_STAGE_FILL 3
+#define SPS_STAGE_SCAN_RESET 4
+#define SPS_STAGE_SCAN_STATS 5
+#define SPS_STAGE_JOIN 6
+#define SPS_STAGE_ESTIMATE 7
+#define SPS_STAGE_SORT 8
+#define SPS_STAGE_FEATURES 9
+#define SPS_STAGE_PROBE 10
+#define SPS_STAGE_MLP 11
+#define SPS_NSTAGES 12
+int sps_profile_enable(int on);
+int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);
+
+/* Roofline probes (measurement only, not part of the method).
+ * sps_probe_scatter: n_stores u16 stores of `value` at uniformly random cells of a device
+ *   array of `cells` u16 (addresses from a counter hash of the store index and seed), one
+ *   store per lane -- the access pattern of the ingest with no hashing of packets.
+ * sps_probe_stream: reads `bytes` (multiple of 16) of device memory with 16-byte lane loads
+ *   and writes one u32 checksum to d_sum -- the access pattern of the scan's first stage. */
+int sps_probe_scatter(uint16_t* d_cells, uint64_t cells, uint64_t n_stores, uint32_t seed,
+                      uint16_t value, void* stream);
+int sps_probe_stream(const void* d_buf, uint64_t bytes, uint32_t* d_sum, void* stream);
 
 /* Wait for all work the library queued on `stream`; reports asynchronous HIP errors. */
 int sps_sync(void* stream);

@@ -10,8 +10,10 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "sps_internal.h"
 
@@ -144,9 +146,98 @@ struct Header {  // 64-byte dump header
 };
 static_assert(sizeof(Header) == 64, "dump header is 64 bytes");
 
+// ---- stage timing ----------------------------------------------------------------------
+std::atomic<bool> g_prof_on{false};
+std::mutex g_prof_mu;
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+};
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_free;
+
+hipEvent_t prof_event() {
+  hipEvent_t e = nullptr;
+  if (!g_prof_free.empty()) {
+    e = g_prof_free.back();
+    g_prof_free.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+int device_cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return n;
+}
+
 }  // namespace
 
+namespace sps {
+ProfScope::ProfScope(int stage, hipStream_t st) : stage_(stage), st_(st), ev0_(nullptr) {
+  if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  hipEvent_t e = prof_event();
+  if (e && hipEventRecord(e, st) == hipSuccess) ev0_ = e;
+}
+ProfScope::~ProfScope() {
+  if (!ev0_) return;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  hipEvent_t e = prof_event();
+  if (e && hipEventRecord(e, st_) == hipSuccess)
+    g_prof_recs.push_back({stage_, static_cast<hipEvent_t>(ev0_), e});
+  else
+    g_prof_free.push_back(static_cast<hipEvent_t>(ev0_));
+}
+}  // namespace sps
+
 extern "C" {
+
+int sps_profile_enable(int on) {
+  g_prof_on.store(on != 0);
+  return SPS_OK;
+}
+
+int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages) {
+  if (!h_ms || !h_launches || nstages < 0) return SPS_EINVAL;
+  for (int i = 0; i < nstages; ++i) {
+    h_ms[i] = 0.0;
+    h_launches[i] = 0;
+  }
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  int rc = SPS_OK;
+  for (const ProfRec& r : g_prof_recs) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) rc = hip_fail(e, "sps_profile_read");
+    if (r.stage < nstages) {
+      h_ms[r.stage] += t;
+      h_launches[r.stage] += 1;
+    }
+    g_prof_free.push_back(r.a);
+    g_prof_free.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  return rc;
+}
+
+int sps_probe_scatter(uint16_t* d_cells, uint64_t cells, uint64_t n_stores, uint32_t seed,
+                      uint16_t value, void* stream) {
+  if (!d_cells || cells == 0) return SPS_EINVAL;
+  SPS_HIP(sps::launch_probe_scatter(d_cells, cells, n_stores, seed, value, device_cu_count(),
+                                    (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_probe_stream(const void* d_buf, uint64_t bytes, uint32_t* d_sum, void* stream) {
+  if (!d_buf || !d_sum || (bytes & 15u)) return SPS_EINVAL;
+  SPS_HIP(sps::launch_probe_stream(d_buf, bytes, d_sum, device_cu_count(), (hipStream_t)stream));
+  return SPS_OK;
+}
 
 const char* sps_strerror(int code) {
   switch (code) {
@@ -369,8 +460,17 @@ int sps_features(const sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_
   return SPS_OK;
 }
 
+int sps_estimate_hosts(sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_t window,
+                       sps_result* d_out, void* stream) {
+  if (!s || (n && (!d_hosts || !d_out))) return SPS_EINVAL;
+  if (window < 1 || window > 65534u || n > 0xFFFFFFFFull) return SPS_EINVAL;
+  SPS_HIP(sps::launch_estimate_hosts(s->dev, s->cur, window, d_hosts, (uint32_t)n, d_out, s->mlp,
+                                     s->n_cu, (hipStream_t)stream));
+  return SPS_OK;
+}
+
 int sps_attach_mlp(sps_sketch* s, const float* d_weights, const float* h_feat_lo,
-                   const float* h_feat_hi, double max_card) {
+                   const float* h_feat_hi, uint32_t min_live, double max_card) {
   if (!s) return SPS_EINVAL;
   if (!d_weights) {
     s->mlp.w = nullptr;
@@ -383,6 +483,44 @@ int sps_attach_mlp(sps_sketch* s, const float* d_weights, const float* h_feat_lo
     s->mlp.hi[i] = h_feat_hi[i];
   }
   s->mlp.log_max = (float)log(max_card);
+  s->mlp.min_live = min_live;
+  return SPS_OK;
+}
+
+int sps_mlp_work_bytes(size_t n, size_t* bytes) {
+  if (!bytes || n == 0 || n > 0xFFFFFFFFull) return SPS_EINVAL;
+  const uint64_t w = sps::mlp_grad_waves((uint32_t)n);
+  *bytes = (size_t)(w * SPS_MLP_PARAMS * 4 + w * 4);
+  return SPS_OK;
+}
+
+int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target,
+                 const uint32_t* d_idx, size_t n, uint32_t etap, void* d_work, float* d_grad,
+                 float* d_loss, void* stream) {
+  if (!d_w || !d_feat || !d_target || !d_work || !d_grad || n == 0 || n > 0xFFFFFFFFull ||
+      etap == 0)
+    return SPS_EINVAL;
+  const uint64_t w = sps::mlp_grad_waves((uint32_t)n);
+  float* partial = static_cast<float*>(d_work);
+  float* partial_loss = partial + w * SPS_MLP_PARAMS;
+  SPS_HIP(sps::launch_mlp_grad(d_w, d_feat, d_target, d_idx, (uint32_t)n, 1.f / (float)etap,
+                               partial, partial_loss, d_grad, d_loss, (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32_t step,
+                 float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!d_w || !d_m || !d_v || !d_grad || step == 0) return SPS_EINVAL;
+  SPS_HIP(sps::launch_mlp_adam(d_w, d_m, d_v, d_grad, step, lr, beta1, beta2, eps,
+                               (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_mlp_forward(const float* d_w, const uint32_t* d_feat, size_t n, uint32_t etap, int bf16,
+                    float* d_y, void* stream) {
+  if (!d_w || (n && (!d_feat || !d_y)) || n > 0xFFFFFFFFull || etap == 0) return SPS_EINVAL;
+  SPS_HIP(sps::launch_mlp_forward(d_w, d_feat, (uint32_t)n, 1.f / (float)etap, bf16, d_y,
+                                  device_cu_count(), (hipStream_t)stream));
   return SPS_OK;
 }
 

@@ -29,6 +29,7 @@ struct MlpRef {
   float lo[SPS_MLP_IN];   // training range of every feature
   float hi[SPS_MLP_IN];
   float log_max;          // outputs above log(max cardinality) fall back
+  uint32_t min_live;      // the network is used only when |USLE|^k >= min_live
 };
 
 // Everything a kernel needs to know about one sketch; passed by value.
@@ -62,6 +63,18 @@ __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
+// Stage timing (sps_api.hip): brackets one launch with HIP events while profiling is on.
+class ProfScope {
+ public:
+  ProfScope(int stage, hipStream_t st);
+  ~ProfScope();
+
+ private:
+  int stage_;
+  hipStream_t st_;
+  void* ev0_;
+};
+
 // Launchers (sps_kernels.hip).
 hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
                          int blocks, int threads, hipStream_t st);
@@ -85,7 +98,24 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st);
+hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_stores,
+                                uint32_t seed, uint16_t value, int n_cu, hipStream_t st);
+hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, int n_cu,
+                               hipStream_t st);
 hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const uint32_t* hosts,
                            uint64_t n, uint32_t* x, int n_cu, hipStream_t st);
+hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
+                                 const uint32_t* hosts, uint32_t n, sps_result* out,
+                                 const MlpRef& mlp, int n_cu, hipStream_t st);
+
+// Learned estimator (sps_mlp.hip).
+uint32_t mlp_grad_waves(uint32_t n);
+hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* target,
+                           const uint32_t* idx, uint32_t n, float inv_norm, float* partial,
+                           float* partial_loss, float* grad, float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint32_t step,
+                           float lr, float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, float inv_norm,
+                              int bf16, float* y, int n_cu, hipStream_t st);
 
 }  // namespace sps

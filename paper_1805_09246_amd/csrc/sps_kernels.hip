@@ -70,6 +70,7 @@ hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t
   if (n == 0) return hipSuccess;
   uint64_t need = (n + threads - 1) / threads;
   if ((uint64_t)blocks > need) blocks = (int)need;
+  ProfScope ps(SPS_STAGE_INGEST, st);
   hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(threads), 0, st, d,
                      reinterpret_cast<const u32x2*>(pkts), n, stamp);
   return hipGetLastError();
@@ -106,6 +107,7 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
   const uint64_t total = t.tile_start[m];
   if (total == 0) return hipSuccess;
   if ((uint64_t)blocks > total) blocks = (int)total;
+  ProfScope ps(SPS_STAGE_INGEST_BATCHED, st);
   hipLaunchKernelGGL(k_ingest_batched, dim3(blocks), dim3(threads), 0, st, shape, t, m, tile,
                      stamp);
   return hipGetLastError();
@@ -126,6 +128,7 @@ hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st) {
   if (nvec == 0) return hipSuccess;
   uint64_t blocks = (nvec + 255) / 256;
   if (blocks > 8192) blocks = 8192;
+  ProfScope ps(SPS_STAGE_FILL, st);
   hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st,
                      reinterpret_cast<u32x4*>(p), nvec);
   return hipGetLastError();
@@ -160,6 +163,7 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
     MergeSrcs s{};
     const uint32_t k = nsrc - b < (uint32_t)kMaxMerge ? nsrc - b : (uint32_t)kMaxMerge;
     for (uint32_t j = 0; j < k; ++j) s.p[j] = reinterpret_cast<const u16x8*>(srcs[b + j]);
+    ProfScope ps(SPS_STAGE_MERGE, st);
     hipLaunchKernelGGL(k_merge_max, dim3((uint32_t)blocks), dim3(256), 0, st,
                        reinterpret_cast<u16x8*>(dst), s, k, nvec);
     hipError_t e = hipGetLastError();
@@ -377,10 +381,15 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
-// Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.
+// Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.  With a host
+// list (`hosts` non-null) every host is estimated and written to direct[c] unfiltered.
 __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t lo, uint32_t k,
-                                                  double threshold, MlpRef mlp) {
-  const uint32_t n = min(d.ctrl->n_cand, d.cand_cap);
+                                                  double threshold, MlpRef mlp,
+                                                  const uint32_t* __restrict__ hosts,
+                                                  uint32_t n_hosts,
+                                                  sps_result* __restrict__ direct) {
+  const uint32_t n = hosts ? n_hosts : min(d.ctrl->n_cand, d.cand_cap);
+  const uint32_t* __restrict__ src = hosts ? hosts : d.cand;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t lane = lane_id();
   const bool use_mlp = mlp.w != nullptr && k == SPS_MLP_IN;
@@ -389,7 +398,7 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
   for (uint32_t i = 0; i < d.rp; ++i)
     P = P * ((double)d.ctrl->row_live[i] / (double)d.row_len);
   for (uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; c < n; c += waves) {
-    const uint32_t x = __builtin_amdgcn_readfirstlane(d.cand[c]);
+    const uint32_t x = __builtin_amdgcn_readfirstlane(src[c]);
     uint32_t U, feat;
     usle_counts(d, x, cur, lo, nfeat, U, feat);
     const double etap = (double)d.etap;
@@ -409,13 +418,13 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
     }
     double est = -etap * log1p(-w / etap);
     if (use_mlp) {
-      // use the network only inside its training range and while some age is unsaturated
+      // the network replaces linear counting only inside its validated domain
       const float f = lane < SPS_MLP_IN ? (float)feat / (float)d.etap : 0.f;
       const bool in_range = lane >= SPS_MLP_IN || (f >= mlp.lo[lane] && f <= mlp.hi[lane]);
       const bool all_in = __ballot(!in_range) == 0;
       const bool informative = __shfl(feat, 0, kWave) < d.etap - 1u;
       const float y = mlp_forward_wave(mlp.w, f);
-      if (all_in && informative && y >= 0.f && y <= mlp.log_max) {
+      if (U >= mlp.min_live && all_in && informative && y >= 0.f && y <= mlp.log_max) {
         est = (double)expf(y);
         flags |= SPS_F_MLP;
       } else {
@@ -423,16 +432,18 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       }
     }
     if (fabs(est - threshold) <= 1e-9 * threshold) flags |= SPS_F_NEAR;
-    if (lane == 0 && est >= threshold) {
-      const uint32_t pos = atomicAdd(&d.ctrl->n_kept, 1u);
-      if (pos < d.cand_cap) {
-        sps_result res;
-        res.host = x;
-        res.live = U;
-        res.flags = flags;
-        res.pad = 0;
-        res.estimate = est;
-        d.kept[pos] = res;
+    if (lane == 0) {
+      sps_result res;
+      res.host = x;
+      res.live = U;
+      res.flags = flags;
+      res.pad = 0;
+      res.estimate = est;
+      if (direct) {
+        direct[c] = res;
+      } else if (est >= threshold) {
+        const uint32_t pos = atomicAdd(&d.ctrl->n_kept, 1u);
+        if (pos < d.cand_cap) d.kept[pos] = res;
       }
     }
   }
@@ -476,7 +487,10 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
-  hipLaunchKernelGGL(k_scan_reset, dim3(1), dim3(64), 0, st, d.ctrl);
+  {
+    ProfScope ps(SPS_STAGE_SCAN_RESET, st);
+    hipLaunchKernelGGL(k_scan_reset, dim3(1), dim3(64), 0, st, d.ctrl);
+  }
   // SLE rows: enough blocks per row that every CU streams, at least 8 vectors per lane
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
@@ -484,12 +498,54 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   if (nb_row > want) nb_row = want;
   if (nb_row < 1) nb_row = 1;
   const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
-  hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row + sre_blocks)), dim3(256), 0,
-                     st, d, lo, (uint32_t)nb_row);
-  hipLaunchKernelGGL(k_join, dim3(n_cu * 4), dim3(256), 0, st, d);
-  hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
-                     threshold, mlp);
-  hipLaunchKernelGGL(k_rank_sort, dim3(n_cu), dim3(256), 0, st, d, out, cap, info);
+  {
+    ProfScope ps(SPS_STAGE_SCAN_STATS, st);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row + sre_blocks)), dim3(256),
+                       0, st, d, lo, (uint32_t)nb_row);
+  }
+  {
+    ProfScope ps(SPS_STAGE_JOIN, st);
+    hipLaunchKernelGGL(k_join, dim3(n_cu * 4), dim3(256), 0, st, d);
+  }
+  {
+    ProfScope ps(SPS_STAGE_ESTIMATE, st);
+    hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
+                       threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr);
+  }
+  {
+    ProfScope ps(SPS_STAGE_SORT, st);
+    hipLaunchKernelGGL(k_rank_sort, dim3(n_cu), dim3(256), 0, st, d, out, cap, info);
+  }
+  return hipGetLastError();
+}
+
+// Estimates of given hosts: SLE row live counts, then the estimate of every host.
+hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
+                                 const uint32_t* hosts, uint32_t n, sps_result* out,
+                                 const MlpRef& mlp, int n_cu, hipStream_t st) {
+  const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
+  {
+    ProfScope ps(SPS_STAGE_SCAN_RESET, st);
+    hipLaunchKernelGGL(k_scan_reset, dim3(1), dim3(64), 0, st, d.ctrl);
+  }
+  const uint64_t nvec_row = d.row_stride / 8;
+  uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
+  const uint64_t want = ((uint64_t)n_cu * 8 + d.rp - 1) / d.rp;
+  if (nb_row > want) nb_row = want;
+  if (nb_row < 1) nb_row = 1;
+  {
+    // only the SLE-array blocks: the SRE part of the grid is not launched
+    ProfScope ps(SPS_STAGE_SCAN_STATS, st);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row)), dim3(256), 0, st, d, lo,
+                       (uint32_t)nb_row);
+  }
+  if (n) {
+    uint32_t blocks = (n + 3) / 4;
+    if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
+    ProfScope ps(SPS_STAGE_ESTIMATE, st);
+    hipLaunchKernelGGL(k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
+                       hosts, n, out);
+  }
   return hipGetLastError();
 }
 
@@ -512,8 +568,54 @@ hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const ui
   if (n == 0) return hipSuccess;
   uint64_t blocks = (n + 3) / 4;
   if (blocks > (uint64_t)n_cu * 8) blocks = (uint64_t)n_cu * 8;
+  ProfScope ps(SPS_STAGE_FEATURES, st);
   hipLaunchKernelGGL(k_features, dim3((uint32_t)blocks), dim3(256), 0, st, d, cur, window,
                      hosts, n, x);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Roofline probes: the ingest's store pattern and the scan's read pattern, without the
+// method's hashing.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_probe_scatter(uint16_t* __restrict__ cells,
+                                                       uint64_t n_cells, uint64_t n,
+                                                       uint32_t seed, uint16_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t h1 = fmix32((uint32_t)i ^ seed);
+    const uint32_t h2 = fmix32((uint32_t)(i >> 32) ^ h1 ^ 0x9E3779B9u);
+    const uint64_t r = ((uint64_t)h1 << 32) | h2;
+    cells[__umul64hi(r, n_cells)] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_probe_stream(const u32x4* __restrict__ buf,
+                                                      uint64_t nvec, uint32_t* sum) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    const u32x4 v = __builtin_nontemporal_load(&buf[i]);
+    acc += v.x ^ v.y ^ v.z ^ v.w;
+  }
+  acc = wave_sum(acc);
+  if (lane_id() == 0) atomicAdd(sum, acc);
+}
+
+hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_stores,
+                                uint32_t seed, uint16_t value, int n_cu, hipStream_t st) {
+  if (n_stores == 0) return hipSuccess;
+  ProfScope ps(SPS_STAGE_PROBE, st);
+  hipLaunchKernelGGL(k_probe_scatter, dim3(n_cu * 16), dim3(256), 0, st, cells, n_cells,
+                     n_stores, seed, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, int n_cu,
+                               hipStream_t st) {
+  ProfScope ps(SPS_STAGE_PROBE, st);
+  hipLaunchKernelGGL(k_probe_stream, dim3(n_cu * 8), dim3(256), 0, st,
+                     reinterpret_cast<const u32x4*>(buf), bytes / 16, sum);
   return hipGetLastError();
 }
 

@@ -29,7 +29,12 @@ EXPORTS = [
     "sps_ingest_batched", "sps_advance", "sps_merge", "sps_scan", "sps_scan_async",
     "sps_features", "sps_attach_mlp", "sps_state_bytes", "sps_export", "sps_import",
     "sps_current_slice", "sps_derived", "sps_debug_copy", "sps_sync", "sps_strerror",
+    "sps_profile_enable", "sps_profile_read", "sps_probe_scatter", "sps_probe_stream",
+    "sps_estimate_hosts", "sps_mlp_work_bytes", "sps_mlp_grad", "sps_mlp_adam",
+    "sps_mlp_forward",
 ]
+STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
+          "estimate", "sort", "features", "probe", "mlp"]
 
 
 class SpsError(RuntimeError):
@@ -73,7 +78,12 @@ def lib():
             "sps_scan": [vp, u32, C.c_double, vp, sz, P(sz), vp],
             "sps_scan_async": [vp, u32, C.c_double, vp, sz, vp, vp],
             "sps_features": [vp, vp, sz, u32, vp, vp],
-            "sps_attach_mlp": [vp, vp, vp, vp, C.c_double],
+            "sps_attach_mlp": [vp, vp, vp, vp, u32, C.c_double],
+            "sps_estimate_hosts": [vp, vp, sz, u32, vp, vp],
+            "sps_mlp_work_bytes": [sz, P(sz)],
+            "sps_mlp_grad": [vp, vp, vp, vp, sz, u32, vp, vp, vp, vp],
+            "sps_mlp_adam": [vp, vp, vp, vp, u32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
+            "sps_mlp_forward": [vp, vp, sz, u32, C.c_int, vp, vp],
             "sps_state_bytes": [vp, P(sz)],
             "sps_export": [vp, vp, sz, vp],
             "sps_import": [vp, vp, sz, vp],
@@ -81,6 +91,10 @@ def lib():
             "sps_derived": [vp, P(u32), P(u32), P(u64)],
             "sps_debug_copy": [vp, i32, vp, sz, P(sz), vp],
             "sps_sync": [vp],
+            "sps_profile_enable": [i32],
+            "sps_profile_read": [vp, vp, i32],
+            "sps_probe_scatter": [vp, u64, u64, u32, C.c_uint16, vp],
+            "sps_probe_stream": [vp, u64, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -200,15 +214,56 @@ def sps_features(h, d_hosts: torch.Tensor, window: int, d_x: torch.Tensor, strea
 
 
 def sps_attach_mlp(h, d_weights: torch.Tensor | None, feat_lo=None, feat_hi=None,
-                   max_card: float = 1e6):
+                   min_live: int = 0, max_card: float = 1e6):
     if d_weights is None:
-        _check(lib().sps_attach_mlp(h, None, None, None, 0.0), "sps_attach_mlp")
+        _check(lib().sps_attach_mlp(h, None, None, None, 0, 0.0), "sps_attach_mlp")
         return
     assert d_weights.dtype == torch.float32 and d_weights.numel() == MLP_PARAMS
     lo = np.ascontiguousarray(feat_lo, dtype=np.float32)
     hi = np.ascontiguousarray(feat_hi, dtype=np.float32)
     _check(lib().sps_attach_mlp(h, _dptr(d_weights), lo.ctypes.data_as(C.c_void_p),
-                                hi.ctypes.data_as(C.c_void_p), max_card), "sps_attach_mlp")
+                                hi.ctypes.data_as(C.c_void_p), int(min_live), max_card),
+           "sps_attach_mlp")
+
+
+def sps_estimate_hosts(h, d_hosts: torch.Tensor, window: int, stream=None) -> torch.Tensor:
+    """Returns a (n * 24)-byte uint8 device tensor of sps_result records (input order)."""
+    n = d_hosts.numel()
+    out = torch.zeros(max(1, n) * 24, dtype=torch.uint8, device=d_hosts.device)
+    _check(lib().sps_estimate_hosts(h, _dptr(d_hosts) if n else None, n, window, _dptr(out),
+                                    _stream(stream)), "sps_estimate_hosts")
+    return out
+
+
+def results_to_numpy(t: torch.Tensor, n: int) -> np.ndarray:
+    return t.cpu().numpy().view(RESULT_DTYPE)[:n]
+
+
+def sps_mlp_work_bytes(n: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().sps_mlp_work_bytes(n, C.byref(b)), "sps_mlp_work_bytes")
+    return b.value
+
+
+def sps_mlp_grad(d_w, d_feat, d_target, d_idx, n: int, etap: int, d_work, d_grad, d_loss=None,
+                 stream=None):
+    _check(lib().sps_mlp_grad(_dptr(d_w), _dptr(d_feat), _dptr(d_target),
+                              _dptr(d_idx) if d_idx is not None else None, n, etap,
+                              _dptr(d_work), _dptr(d_grad),
+                              _dptr(d_loss) if d_loss is not None else None, _stream(stream)),
+           "sps_mlp_grad")
+
+
+def sps_mlp_adam(d_w, d_m, d_v, d_grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+    _check(lib().sps_mlp_adam(_dptr(d_w), _dptr(d_m), _dptr(d_v), _dptr(d_grad), step, lr, beta1,
+                              beta2, eps, _stream(stream)), "sps_mlp_adam")
+
+
+def sps_mlp_forward(d_w, d_feat, n: int, etap: int, bf16: bool, d_y, stream=None):
+    _check(lib().sps_mlp_forward(_dptr(d_w), _dptr(d_feat) if n else None, n, etap,
+                                 1 if bf16 else 0, _dptr(d_y) if n else None, _stream(stream)),
+           "sps_mlp_forward")
 
 
 def sps_state_bytes(h) -> int:
@@ -259,6 +314,32 @@ def sps_sync(stream=None):
 
 def sps_strerror(code: int) -> str:
     return strerror(code)
+
+
+def sps_profile_enable(on: bool):
+    _check(lib().sps_profile_enable(1 if on else 0), "sps_profile_enable")
+
+
+def sps_profile_read() -> dict:
+    """{stage name: (total ms, launches)} since the last read (synchronizes)."""
+    n = len(STAGES)
+    ms = np.zeros(n, dtype=np.float64)
+    cnt = np.zeros(n, dtype=np.uint32)
+    _check(lib().sps_profile_read(ms.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p),
+                                  n), "sps_profile_read")
+    return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def sps_probe_scatter(d_cells: torch.Tensor, n_stores: int, seed: int, value: int, stream=None):
+    assert d_cells.element_size() == 2
+    _check(lib().sps_probe_scatter(_dptr(d_cells), d_cells.numel(), n_stores, seed, value,
+                                   _stream(stream)), "sps_probe_scatter")
+
+
+def sps_probe_stream(d_buf: torch.Tensor, d_sum: torch.Tensor, stream=None):
+    nbytes = d_buf.numel() * d_buf.element_size()
+    _check(lib().sps_probe_stream(_dptr(d_buf), nbytes, _dptr(d_sum), _stream(stream)),
+           "sps_probe_stream")
 
 
 # ---------------------------------------------------------------- convenience owner

@@ -130,3 +130,69 @@ def make_stream(rec: StreamRecipe) -> Stream:
 
 def log_uniform_int(rng: np.random.Generator, lo: float, hi: float, n: int) -> list:
     return [int(round(math.exp(v))) for v in rng.uniform(math.log(lo), math.log(hi), n)]
+
+
+@dataclasses.dataclass
+class MultiRecipe:
+    """m routers that see one host population.  Router j's background packet count over the
+    whole run is T_j = round(median * exp(sigma * Z_j)), Z_j ~ N(0, 1); every planted host
+    emits ceil(c / window) fresh peers per slice, each packet to a uniformly drawn router
+    (so only the merged view holds a planted host's full cardinality).  Planted packets come
+    on top of the background counts."""
+    name: str
+    seed: int
+    n_routers: int
+    median: int
+    sigma: float
+    n_slices: int
+    window: int
+    n_hosts: int
+    zipf_s: float
+    planted: list
+
+
+def router_totals(rec: MultiRecipe) -> np.ndarray:
+    rng = np.random.Generator(np.random.Philox(rec.seed ^ 0x7070))
+    z = rng.standard_normal(rec.n_routers)
+    return np.round(rec.median * np.exp(rec.sigma * z)).astype(np.int64)
+
+
+def make_multi_stream(rec: MultiRecipe) -> list:
+    """One Stream per router (slices numbered from 1)."""
+    rng = np.random.Generator(np.random.Philox(rec.seed))
+    cdf = zipf_cdf(rec.n_hosts, rec.zipf_s)
+    totals = router_totals(rec)
+    planted = np.asarray(rec.planted, dtype=np.int64)
+    n_pl = len(planted)
+    per_slice = np.ceil(planted / rec.window).astype(np.int64) if n_pl else np.zeros(0, np.int64)
+    planted_hosts = addr_mix(np.arange(rec.n_hosts + 1, rec.n_hosts + 1 + n_pl, dtype=np.uint64)
+                             .astype(np.uint32), HOST_SALT)
+    pl_dst = np.repeat(planted_hosts, per_slice)
+    pl_j = np.repeat(np.arange(n_pl, dtype=np.uint32), per_slice)
+    pl_t_base = (np.concatenate([np.arange(m, dtype=np.uint32) for m in per_slice]) if n_pl
+                 else np.zeros(0, np.uint32))
+    bg_sizes = [slice_sizes(int(t), rec.n_slices) for t in totals]
+    chunks = [[] for _ in range(rec.n_routers)]
+    for s in range(rec.n_slices):
+        t = pl_t_base + (np.repeat(per_slice, per_slice).astype(np.uint32) * np.uint32(s)
+                         if n_pl else np.zeros(0, np.uint32))
+        pl_src = addr_mix(((pl_j + np.uint32(1)) << np.uint32(24)) | t, PEER_SALT)
+        who = rng.integers(0, rec.n_routers, size=pl_src.shape[0])
+        for r in range(rec.n_routers):
+            nb = int(bg_sizes[r][s])
+            bg_dst = addr_mix(zipf_ranks(rng, cdf, nb), HOST_SALT)
+            bg_src = addr_mix(rng.integers(0, 1 << 24, size=nb, dtype=np.uint32), PEER_SALT)
+            mine = who == r
+            src = np.concatenate([bg_src, pl_src[mine]])
+            dst = np.concatenate([bg_dst, pl_dst[mine]])
+            perm = rng.permutation(src.shape[0])
+            chunks[r].append(np.stack([src[perm], dst[perm]], 1))
+    out = []
+    for r in range(rec.n_routers):
+        sizes = np.array([c.shape[0] for c in chunks[r]], dtype=np.int64)
+        off = np.zeros(rec.n_slices + 1, dtype=np.int64)
+        off[1:] = np.cumsum(sizes)
+        srec = StreamRecipe(f"{rec.name}/router{r}", rec.seed, int(off[-1]), rec.n_slices,
+                            rec.window, rec.n_hosts, rec.zipf_s, list(rec.planted))
+        out.append(Stream(srec, np.concatenate(chunks[r]), off, planted_hosts, per_slice))
+    return out

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import StreamRecipe, log_uniform_int
+from . import MultiRecipe, StreamRecipe, log_uniform_int
 
 
 def sketch_params(q, r, delta, eta, qp, rp, etap, deltap, theta, seed, anet_side=0):
@@ -44,3 +44,23 @@ C2_WINDOW, C2_THRESHOLD = 10, 1024.0
 C2_SMALL_RECIPE = StreamRecipe(name="c2_shape_small_stream", seed=0x180509246012,
                                n_packets=3 << 20, n_slices=12, window=10, n_hosts=1 << 22,
                                zipf_s=1.05, planted=[1500, 3000, 6000, 12000, 40000])
+
+
+def _c3_planted():
+    rng = np.random.Generator(np.random.Philox(0x180509246003 ^ 0xFACE))
+    return log_uniform_int(rng, 1e3, 1e5, 200)
+
+
+# Distributed merge on one GPU: 16 routers, lognormal packet counts (median 2^22, sigma 1)
+# over 30 slices; merged by element-wise max, scanned with window 10 and threshold 2048.
+C3_RECIPE = MultiRecipe(name="c3_distributed_merge_16", seed=0x180509246003, n_routers=16,
+                        median=1 << 22, sigma=1.0, n_slices=30, window=10, n_hosts=1 << 22,
+                        zipf_s=1.05, planted=_c3_planted())
+C3_PARAMS = sketch_params(q=17, r=5, delta=5, eta=8, qp=16, rp=5, etap=1024, deltap=1024,
+                          theta=2048, seed=0x5A5A180509246003)
+C3_WINDOW, C3_THRESHOLD = 10, 2048.0
+
+# The same sketch shapes with small routers: the parity tests' case of the merge workload.
+C3_SMALL_RECIPE = MultiRecipe(name="c3_shape_small", seed=0x180509246013, n_routers=16,
+                              median=1 << 17, sigma=1.0, n_slices=12, window=10,
+                              n_hosts=1 << 20, zipf_s=1.05, planted=[3000, 8000, 20000, 60000])

@@ -1,0 +1,169 @@
+"""Learned estimator on the GPU: forward / gradient / Adam kernels against the fp64 oracle,
+the generator against its CPU twin, in-scan inference and gating, and what the trained
+network gains over linear counting on held-out hosts."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as omlp
+from paper_1805_09246_amd import learned, sps
+
+pytestmark = pytest.mark.gpu
+
+ETAP = 1024
+
+
+def _feat(rng, n):
+    # monotone per-age counts like real features: cumulative sums of random increments
+    inc = rng.integers(0, 160, size=(n, 10))
+    return np.minimum(np.cumsum(inc, 1), ETAP).astype(np.uint32)
+
+
+def _params_np(seed):
+    p = omlp.init_params(seed)
+    for k in p:
+        p[k] = p[k] + np.random.default_rng(seed).normal(0, 0.05, p[k].shape)
+    return p
+
+
+def _dev(a, dt=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+
+
+def test_forward_fp32_and_bf16():
+    rng = np.random.default_rng(0)
+    p = _params_np(3)
+    x = _feat(rng, 3000)
+    want, _ = omlp.forward(p, x / ETAP)
+    w = _dev(omlp.flatten(p).astype(np.float32))
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    y = torch.zeros(3000, dtype=torch.float32, device="cuda")
+    sps.sps_mlp_forward(w, xd, 3000, ETAP, False, y)
+    got = y.cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-4 * max(1.0, np.max(np.abs(want)))
+    sps.sps_mlp_forward(w, xd, 3000, ETAP, True, y)
+    got16 = y.cpu().numpy()
+    rel = np.abs(got16 - want) / np.maximum(1.0, np.abs(want))
+    assert rel.max() <= 2e-2
+
+
+@pytest.mark.parametrize("n", [1, 37, 4096, 20000])
+def test_gradient_against_fp64(n):
+    rng = np.random.default_rng(n)
+    p = _params_np(5)
+    x = _feat(rng, n + 11)
+    t = rng.uniform(0, 12, n + 11)
+    idx = rng.permutation(n + 11)[:n].astype(np.int32)
+    loss_ref, g_ref = omlp.loss_and_grad(p, x[idx] / ETAP, t[idx])
+    gv = omlp.flatten(g_ref)
+    w = _dev(omlp.flatten(p).astype(np.float32))
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    td = _dev(t.astype(np.float32))
+    idd = torch.from_numpy(idx).cuda()
+    work = torch.empty(sps.sps_mlp_work_bytes(n), dtype=torch.uint8, device="cuda")
+    grad = torch.zeros(sps.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sps.sps_mlp_grad(w, xd, td, idd, n, ETAP, work, grad, loss)
+    got = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - gv) <= 1e-3 * np.linalg.norm(gv)
+    big = np.abs(gv) > 1e-2 * np.abs(gv).max()
+    assert np.all(np.abs(got[big] - gv[big]) <= 1e-3 * np.abs(gv[big]) + 1e-5 * np.abs(gv).max())
+    assert abs(loss.item() - loss_ref) <= 1e-4 * loss_ref
+    # deterministic: a second call gives the same bits
+    g2 = torch.zeros_like(grad)
+    sps.sps_mlp_grad(w, xd, td, idd, n, ETAP, work, g2, loss)
+    assert torch.equal(g2, grad)
+
+
+def test_adam_step_against_fp64():
+    rng = np.random.default_rng(1)
+    p = _params_np(7)
+    g = {k: rng.normal(0, 1e-2, v.shape) for k, v in p.items()}
+    m = {k: rng.normal(0, 1e-3, v.shape) for k, v in p.items()}
+    v = {k: rng.uniform(0, 1e-4, v_.shape) for k, v_ in p.items()}
+    p1, m1, v1 = omlp.adam_step(p, g, m, v, 7, lr=1e-3)
+    wd = _dev(omlp.flatten(p).astype(np.float32))
+    md = _dev(omlp.flatten(m).astype(np.float32))
+    vd = _dev(omlp.flatten(v).astype(np.float32))
+    gd = _dev(omlp.flatten(g).astype(np.float32))
+    sps.sps_mlp_adam(wd, md, vd, gd, 7, 1e-3)
+    for got, want in ((wd, p1), (md, m1), (vd, v1)):
+        a = got.cpu().numpy().astype(np.float64)
+        b = omlp.flatten(want)
+        assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-6)) <= 1e-4
+
+
+def test_generator_matches_cpu_twin():
+    from synth import learned as L
+    cards = np.array([1, 7, 100, 3000, 20000, 5], dtype=np.int64)
+    hosts = L.host_addrs(0, len(cards))
+    salts = L.peer_salts(11, len(cards))
+    want = L.planted_cpu(hosts, cards, salts, key=1234)
+    gen = L.PlantedGenerator(int(cards.sum()) + 10)
+    got = gen.generate(hosts, cards, salts, key=1234)
+    assert sum(len(b) for b in want) == cards.sum()
+    for s in range(10):
+        gs = got[s].cpu().numpy().view(np.uint32)
+        gs = gs[np.lexsort((gs[:, 0], gs[:, 1]))]
+        assert np.array_equal(gs, want[s]), f"slice {s + 1}"
+
+
+def test_scan_inference_and_gating():
+    """Attached network: in-scan estimates equal the batched bf16 forward where the gate
+    admits it, linear counting elsewhere; the LC estimates equal the oracle's."""
+    from synth.configs import C2_PARAMS
+    params = dict(C2_PARAMS, qp=12)
+    ds_sk = sps.Sketch(params)
+    o = oracle.OracleSketch(params)
+    rng = np.random.default_rng(4)
+    from synth import learned as L
+    cards = np.array([50, 400, 2000, 6000, 9000, 15000, 40000, 3], dtype=np.int64)
+    hosts = L.host_addrs(500, len(cards))
+    buckets = L.planted_cpu(hosts, cards, L.peer_salts(3, len(cards)), key=77)
+    for s in range(1, 11):
+        bg = rng.integers(0, 1 << 32, size=(20000, 2), dtype=np.uint64).astype(np.uint32)
+        p = np.concatenate([buckets[s - 1], bg])
+        ds_sk.ingest(torch.from_numpy(p.view(np.int32)).cuda(), s)
+        o.ingest(p, s)
+    hd = torch.from_numpy(hosts.view(np.int32)).cuda()
+    lc = sps.results_to_numpy(sps.sps_estimate_hosts(ds_sk.h, hd, 10), len(hosts))
+    rl = o.row_live(10)
+    x = o.features(10, hosts)
+    for i, h in enumerate(hosts):
+        est, fl = o.estimate_one(int(x[i, -1]), rl, 0.0)
+        assert abs(lc["estimate"][i] - est) <= 4 * np.spacing(est) and lc["flags"][i] == fl
+    w = _dev(omlp.flatten(_params_np(9)).astype(np.float32))
+    gate = learned.Gate(np.zeros(10, np.float32), np.ones(10, np.float32), 100, 1e9)
+    learned.attach(ds_sk.h, w, gate)
+    ml = sps.results_to_numpy(sps.sps_estimate_hosts(ds_sk.h, hd, 10), len(hosts))
+    ds = learned.Dataset(x, cards, lc["estimate"], lc["flags"], params["etap"])
+    y = learned.predict(w, ds, bf16=True)
+    want, use = learned.gated(ds, y, gate)
+    assert np.array_equal((ml["flags"] & sps.F_MLP) != 0, use)
+    assert np.all((ml["flags"][~use] & sps.F_LC_FALLBACK) != 0)
+    assert np.allclose(ml["estimate"][use], want[use], rtol=1e-5)
+    assert np.array_equal(ml["estimate"][~use], lc["estimate"][~use])
+
+
+@pytest.mark.slow
+def test_trained_network_beats_linear_counting():
+    """Train on generated hosts with the library's kernels; on held-out hosts the gated
+    network's mean relative error is at or below linear counting's, and lower where linear
+    counting saturates."""
+    from synth.configs import C2_PARAMS
+    params = dict(C2_PARAMS)
+    tr = learned.generate(params, 60000, seed=0x5EED01, log=print)
+    va = learned.generate(params, 10000, seed=0x5EED02, log=print)
+    te = learned.generate(params, 20000, seed=0x5EED03, log=print)
+    w = learned.train(tr, epochs=25, batch=2048, lr=3e-3, log=print)
+    gate = learned.fit_gate(tr, va, learned.predict(w, va))
+    est, use = learned.gated(te, learned.predict(w, te), gate)
+    e_lc = np.abs(te.lc - te.cards) / te.cards
+    e_ml = np.abs(est - te.cards) / te.cards
+    print("min_live", gate.min_live, "LC", e_lc.mean(), "MLP", e_ml.mean(), "used", use.mean())
+    assert e_ml.mean() <= e_lc.mean()
+    sat = (te.cards >= 8000) & (te.cards < 20000)
+    assert e_ml[sat].mean() < e_lc[sat].mean()
