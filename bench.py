@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the "
@@ -120,6 +122,14 @@ def main():
     from synth.configs import C2_PARAMS, C2_RECIPE, C2_THRESHOLD, C2_WINDOW
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel()}), flush=True)
+        return
     rec, params, K_WIN, THETA = C2_RECIPE, C2_PARAMS, C2_WINDOW, C2_THRESHOLD
     t0 = time.perf_counter()
     st = make_stream(rec)
