@@ -128,6 +128,39 @@ int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, v
 int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
                        uint32_t m, uint32_t slice, void* stream);
 
+/* Launch shape of the ingest kernels: blocks per compute unit for sps_ingest and
+ * sps_ingest_batched, and the tile (pairs per work item) of sps_ingest_batched.  Chosen by
+ * sps_autotune_ingest or set directly (0 keeps the current value). */
+typedef struct sps_tuning {
+  uint32_t blocks_per_cu;
+  uint32_t batch_tile;
+} sps_tuning;
+int sps_get_tuning(const sps_sketch* s, sps_tuning* out);
+int sps_set_tuning(sps_sketch* s, const sps_tuning* t);
+
+/* Autotuner: ingests the given batch (exactly like sps_ingest_batched; for m == 1 like
+ * sps_ingest) once per candidate launch shape, timing each with HIP events, and keeps the
+ * fastest shape in every sketch of h_s.  Re-ingesting the same pairs at the same slice is
+ * idempotent, so the resulting state equals a single ingest.  Synchronous.  *best (may be
+ * NULL) receives the chosen shape; h_ms (may be NULL, h_ms_cap entries) the time of each
+ * candidate in the order tried. */
+int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
+                        uint32_t m, uint32_t slice, void* stream, sps_tuning* best,
+                        float* h_ms, uint32_t h_ms_cap);
+
+/* ---- stream capture ------------------------------------------------------------------------
+ * Every library call that only launches kernels (ingest, batched ingest, reset, merge,
+ * scan_async, features, estimate_hosts, mlp_*) may be captured.  sps_graph_begin starts
+ * capturing `stream`; sps_graph_end ends it and instantiates the graph; sps_graph_launch
+ * replays it on a stream.  Host-side state (the current slice) is updated when the call is
+ * captured, so a captured slice is meant to be launched once (replays of an ingest are
+ * idempotent). */
+typedef struct sps_graph sps_graph;
+int sps_graph_begin(void* stream);
+int sps_graph_end(void* stream, sps_graph** out);
+int sps_graph_launch(sps_graph* g, void* stream);
+int sps_graph_destroy(sps_graph* g);
+
 /* Time passes with no packets: set the current slice (same rules as sps_ingest). */
 int sps_advance(sps_sketch* s, uint32_t slice);
 

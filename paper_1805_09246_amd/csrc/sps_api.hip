@@ -36,7 +36,7 @@ struct sps_sketch {
   uint32_t cur;
   int device;
   int n_cu;
-  int ingest_blocks;
+  sps_tuning tune;
 };
 
 namespace {
@@ -179,6 +179,8 @@ int device_cu_count() {
 namespace sps {
 ProfScope::ProfScope(int stage, hipStream_t st) : stage_(stage), st_(st), ev0_(nullptr) {
   if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> g(g_prof_mu);
   hipEvent_t e = prof_event();
   if (e && hipEventRecord(e, st) == hipSuccess) ev0_ = e;
@@ -330,7 +332,8 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   s->state_cells = (L.slea - L.sre) / 2 + L.slea_cells;
   s->cur = 0;
   s->mlp.w = nullptr;
-  s->ingest_blocks = s->n_cu * 16;
+  s->tune.blocks_per_cu = 16;
+  s->tune.batch_tile = 4096;
   // zero state and workspace once, synchronously
   SPS_HIP(hipMemset(s->base, 0, L.total));
   SPS_HIP(hipDeviceSynchronize());
@@ -358,14 +361,38 @@ int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, v
   if (!s || (n && !d_pkts)) return SPS_EINVAL;
   int rc = check_slice(s, slice);
   if (rc) return rc;
-  SPS_HIP(sps::launch_ingest(s->dev, d_pkts, n, (uint16_t)slice, s->ingest_blocks, 256,
-                             (hipStream_t)stream));
+  SPS_HIP(sps::launch_ingest(s->dev, d_pkts, n, (uint16_t)slice,
+                             s->n_cu * (int)s->tune.blocks_per_cu, 256, (hipStream_t)stream));
   s->cur = slice;
   return SPS_OK;
 }
 
-int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
-                       uint32_t m, uint32_t slice, void* stream) {
+namespace {
+// Validate a batch and launch it with the given shape (64 routers per launch).
+int ingest_batched_with(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
+                        uint32_t m, uint32_t slice, hipStream_t st, const sps_tuning& t) {
+  const uint32_t tile = t.batch_tile;
+  for (uint32_t b = 0; b < m; b += sps::kMaxBatch) {
+    const uint32_t k = m - b < (uint32_t)sps::kMaxBatch ? m - b : (uint32_t)sps::kMaxBatch;
+    sps::BatchTable tb{};
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+      tb.item[j].sre = h_s[b + j]->dev.sre;
+      tb.item[j].slea = h_s[b + j]->dev.slea;
+      tb.item[j].pkts = h_pkts[b + j];
+      tb.item[j].n = h_n[b + j];
+      tb.tile_start[j] = acc;
+      acc += (h_n[b + j] + tile - 1) / tile;
+    }
+    tb.tile_start[k] = acc;
+    SPS_HIP(sps::launch_ingest_batched(h_s[0]->dev, tb, k, tile, (uint16_t)slice,
+                                       h_s[0]->n_cu * (int)t.blocks_per_cu, 256, st));
+  }
+  return SPS_OK;
+}
+
+int check_batch(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
+                uint32_t m, uint32_t slice) {
   if (!h_s || !h_pkts || !h_n || m == 0) return SPS_EINVAL;
   for (uint32_t j = 0; j < m; ++j) {
     if (!h_s[j] || (h_n[j] && !h_pkts[j])) return SPS_EINVAL;
@@ -373,24 +400,133 @@ int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, con
     int rc = check_slice(h_s[j], slice);
     if (rc) return rc;
   }
-  const uint32_t tile = 4096;
-  for (uint32_t b = 0; b < m; b += sps::kMaxBatch) {
-    const uint32_t k = m - b < (uint32_t)sps::kMaxBatch ? m - b : (uint32_t)sps::kMaxBatch;
-    sps::BatchTable t{};
-    uint64_t acc = 0;
-    for (uint32_t j = 0; j < k; ++j) {
-      t.item[j].sre = h_s[b + j]->dev.sre;
-      t.item[j].slea = h_s[b + j]->dev.slea;
-      t.item[j].pkts = h_pkts[b + j];
-      t.item[j].n = h_n[b + j];
-      t.tile_start[j] = acc;
-      acc += (h_n[b + j] + tile - 1) / tile;
-    }
-    t.tile_start[k] = acc;
-    SPS_HIP(sps::launch_ingest_batched(h_s[0]->dev, t, k, tile, (uint16_t)slice,
-                                       h_s[0]->n_cu * 16, 256, (hipStream_t)stream));
-  }
+  return SPS_OK;
+}
+}  // namespace
+
+int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
+                       uint32_t m, uint32_t slice, void* stream) {
+  int rc = check_batch(h_s, h_pkts, h_n, m, slice);
+  if (rc) return rc;
+  rc = ingest_batched_with(h_s, h_pkts, h_n, m, slice, (hipStream_t)stream, h_s[0]->tune);
+  if (rc) return rc;
   for (uint32_t j = 0; j < m; ++j) h_s[j]->cur = slice;
+  return SPS_OK;
+}
+
+int sps_get_tuning(const sps_sketch* s, sps_tuning* out) {
+  if (!s || !out) return SPS_EINVAL;
+  *out = s->tune;
+  return SPS_OK;
+}
+
+int sps_set_tuning(sps_sketch* s, const sps_tuning* t) {
+  if (!s || !t) return SPS_EINVAL;
+  if (t->blocks_per_cu > 256 || (t->batch_tile && (t->batch_tile < 64 || t->batch_tile > (1u << 24))))
+    return SPS_EINVAL;
+  if (t->blocks_per_cu) s->tune.blocks_per_cu = t->blocks_per_cu;
+  if (t->batch_tile) s->tune.batch_tile = t->batch_tile;
+  return SPS_OK;
+}
+
+int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
+                        uint32_t m, uint32_t slice, void* stream, sps_tuning* best,
+                        float* h_ms, uint32_t h_ms_cap) {
+  int rc = check_batch(h_s, h_pkts, h_n, m, slice);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  static const uint32_t kBlocks[] = {2, 4, 8, 16, 32, 64};
+  static const uint32_t kTiles[] = {512, 2048, 8192, 32768};
+  std::vector<sps_tuning> cands;
+  for (uint32_t b : kBlocks) {
+    if (m == 1) {
+      cands.push_back({b, h_s[0]->tune.batch_tile});
+    } else {
+      for (uint32_t t : kTiles) cands.push_back({b, t});
+    }
+  }
+  hipEvent_t e0, e1;
+  SPS_HIP(hipEventCreate(&e0));
+  SPS_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  sps_tuning pick = h_s[0]->tune;
+  uint32_t idx = 0;
+  for (int rep = 0; rep < 2; ++rep) {  // first pass warms caches, second pass is timed
+    for (const sps_tuning& c : cands) {
+      SPS_HIP(hipEventRecord(e0, st));
+      if (m == 1) {
+        SPS_HIP(sps::launch_ingest(h_s[0]->dev, h_pkts[0], h_n[0], (uint16_t)slice,
+                                   h_s[0]->n_cu * (int)c.blocks_per_cu, 256, st));
+      } else {
+        rc = ingest_batched_with(h_s, h_pkts, h_n, m, slice, st, c);
+        if (rc) return rc;
+      }
+      SPS_HIP(hipEventRecord(e1, st));
+      SPS_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SPS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep == 1) {
+        if (h_ms && idx < h_ms_cap) h_ms[idx] = ms;
+        ++idx;
+        if (ms < best_ms) {
+          best_ms = ms;
+          pick = c;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (uint32_t j = 0; j < m; ++j) {
+    h_s[j]->tune = pick;
+    h_s[j]->cur = slice;
+  }
+  if (best) *best = pick;
+  return SPS_OK;
+}
+
+struct sps_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int sps_graph_begin(void* stream) {
+  SPS_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  return SPS_OK;
+}
+
+int sps_graph_end(void* stream, sps_graph** out) {
+  if (!out) return SPS_EINVAL;
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  SPS_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
+  hipGraphExec_t e = nullptr;
+  hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  if (err != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(err, "hipGraphInstantiate");
+  }
+  sps_graph* r = new (std::nothrow) sps_graph{g, e};
+  if (!r) {
+    (void)hipGraphExecDestroy(e);
+    (void)hipGraphDestroy(g);
+    return SPS_ENOMEM;
+  }
+  *out = r;
+  return SPS_OK;
+}
+
+int sps_graph_launch(sps_graph* g, void* stream) {
+  if (!g) return SPS_EINVAL;
+  SPS_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_graph_destroy(sps_graph* g) {
+  if (!g) return SPS_EINVAL;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
   return SPS_OK;
 }
 

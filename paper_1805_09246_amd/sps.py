@@ -31,10 +31,15 @@ EXPORTS = [
     "sps_current_slice", "sps_derived", "sps_debug_copy", "sps_sync", "sps_strerror",
     "sps_profile_enable", "sps_profile_read", "sps_probe_scatter", "sps_probe_stream",
     "sps_estimate_hosts", "sps_mlp_work_bytes", "sps_mlp_grad", "sps_mlp_adam",
-    "sps_mlp_forward",
+    "sps_mlp_forward", "sps_get_tuning", "sps_set_tuning", "sps_autotune_ingest",
+    "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
           "estimate", "sort", "features", "probe", "mlp"]
+
+
+class sps_tuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_uint32), ("batch_tile", C.c_uint32)]
 
 
 class SpsError(RuntimeError):
@@ -84,6 +89,13 @@ def lib():
             "sps_mlp_grad": [vp, vp, vp, vp, sz, u32, vp, vp, vp, vp],
             "sps_mlp_adam": [vp, vp, vp, vp, u32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
             "sps_mlp_forward": [vp, vp, sz, u32, C.c_int, vp, vp],
+            "sps_get_tuning": [vp, P(sps_tuning)],
+            "sps_set_tuning": [vp, P(sps_tuning)],
+            "sps_autotune_ingest": [P(vp), P(vp), P(sz), u32, u32, vp, P(sps_tuning), vp, u32],
+            "sps_graph_begin": [vp],
+            "sps_graph_end": [vp, P(vp)],
+            "sps_graph_launch": [vp, vp],
+            "sps_graph_destroy": [vp],
             "sps_state_bytes": [vp, P(sz)],
             "sps_export": [vp, vp, sz, vp],
             "sps_import": [vp, vp, sz, vp],
@@ -340,6 +352,49 @@ def sps_probe_stream(d_buf: torch.Tensor, d_sum: torch.Tensor, stream=None):
     nbytes = d_buf.numel() * d_buf.element_size()
     _check(lib().sps_probe_stream(_dptr(d_buf), nbytes, _dptr(d_sum), _stream(stream)),
            "sps_probe_stream")
+
+
+def sps_get_tuning(h) -> dict:
+    t = sps_tuning()
+    _check(lib().sps_get_tuning(h, C.byref(t)), "sps_get_tuning")
+    return {"blocks_per_cu": t.blocks_per_cu, "batch_tile": t.batch_tile}
+
+
+def sps_set_tuning(h, blocks_per_cu: int = 0, batch_tile: int = 0):
+    t = sps_tuning(blocks_per_cu, batch_tile)
+    _check(lib().sps_set_tuning(h, C.byref(t)), "sps_set_tuning")
+
+
+def sps_autotune_ingest(hs, pkts_list, slice_: int, stream=None):
+    """Returns (best tuning dict, list of candidate times in ms)."""
+    m = len(hs)
+    harr = (C.c_void_p * m)(*[h.value for h in hs])
+    parr = (C.c_void_p * m)(*[(p.data_ptr() if p.shape[0] else 0) for p in pkts_list])
+    narr = (C.c_size_t * m)(*[p.shape[0] for p in pkts_list])
+    best = sps_tuning()
+    ms = np.zeros(64, dtype=np.float32)
+    _check(lib().sps_autotune_ingest(harr, parr, narr, m, slice_, _stream(stream), C.byref(best),
+                                     ms.ctypes.data_as(C.c_void_p), 64), "sps_autotune_ingest")
+    n = 6 if m == 1 else 24
+    return {"blocks_per_cu": best.blocks_per_cu, "batch_tile": best.batch_tile}, ms[:n].tolist()
+
+
+def sps_graph_begin(stream=None):
+    _check(lib().sps_graph_begin(_stream(stream)), "sps_graph_begin")
+
+
+def sps_graph_end(stream=None):
+    g = C.c_void_p(0)
+    _check(lib().sps_graph_end(_stream(stream), C.byref(g)), "sps_graph_end")
+    return g
+
+
+def sps_graph_launch(g, stream=None):
+    _check(lib().sps_graph_launch(g, _stream(stream)), "sps_graph_launch")
+
+
+def sps_graph_destroy(g):
+    _check(lib().sps_graph_destroy(g), "sps_graph_destroy")
 
 
 # ---------------------------------------------------------------- convenience owner
