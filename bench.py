@@ -99,6 +99,76 @@ def cpu_baseline(stream, params, window, threshold, n_slices_sample=10, n_scans=
     }
 
 
+def serving_extra(pool, log_fn):
+    """Config 4: the serving loop in real time; p50/p99 arrival-to-report latency."""
+    import numpy as np
+    from paper_1805_09246_amd.serve import Server, poisson_schedule, run_simulation
+    from synth.configs import (C4_BUDGET, C4_PARAMS, C4_RATE, C4_ROUTERS, C4_SEED, C4_SLICE_S,
+                               C4_SLICES, C4_THRESHOLD, C4_WINDOW)
+    srv = Server(C4_PARAMS, C4_WINDOW, C4_THRESHOLD, C4_BUDGET)
+    for r in range(C4_ROUTERS):
+        srv.admit(r)
+    sched = poisson_schedule(C4_SEED, C4_RATE, C4_SLICES * C4_SLICE_S, C4_ROUTERS)
+    wall, n_pk = run_simulation(srv, pool, sched, C4_SLICE_S, C4_SLICES)
+    lat = np.array([x for r in srv.reports for x in r.latencies])
+    slices_done = max(r.slice for r in srv.reports)
+    log_fn(f"serving: {len(lat)} batches, {n_pk} packets in {wall:.2f} s")
+    out = {
+        "workload": f"{C4_ROUTERS} routers, Poisson batches 4Ki-4Mi at {C4_RATE:.0e} pkt/s, "
+                    f"{C4_SLICES} slices of {C4_SLICE_S * 1e3:.0f} ms, window {C4_WINDOW}",
+        "packets_per_s": n_pk / wall,
+        "offered_packets_per_s": C4_RATE,
+        "batches": int(len(lat)),
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "max_latency_ms": float(lat.max() * 1e3),
+        "slices": slices_done,
+        "wall_s": wall,
+        "resident_sketches": len(srv.slots),
+        "resident_GiB": srv.used_bytes() / 2 ** 30,
+    }
+    for s in srv.slots:
+        s.sketch.close()
+    return out
+
+
+def learned_extra(log_fn):
+    """Config 5: train the estimator on generated hosts; held-out error vs linear counting."""
+    import numpy as np
+    from paper_1805_09246_amd import learned
+    from synth.configs import C5_PARAMS, C5_SEEDS, C5_TEST, C5_TRAIN, C5_VAL
+    t0 = time.perf_counter()
+    bases = learned.make_backgrounds(C5_PARAMS, C5_SEEDS[0])
+    tr = learned.generate(C5_PARAMS, C5_TRAIN, C5_SEEDS[0], bases=bases, log=log_fn)
+    va = learned.generate(C5_PARAMS, C5_VAL, C5_SEEDS[1], bases=bases)
+    te = learned.generate(C5_PARAMS, C5_TEST, C5_SEEDS[2], bases=bases)
+    for b in bases:
+        b.close()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w = learned.train(tr, epochs=20, batch=4096, lr=3e-3, log=log_fn)
+    import torch
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    gate = learned.fit_gate(tr, va, learned.predict(w, va))
+    est, use = learned.gated(te, learned.predict(w, te), gate)
+    e_lc = np.abs(te.lc - te.cards) / te.cards
+    e_ml = np.abs(est - te.cards) / te.cards
+    return {
+        "workload": f"{C5_TRAIN} training / {C5_VAL} validation / {C5_TEST} held-out hosts, "
+                    "cardinality log-uniform 1..1e6, window 10",
+        "lc_mean_rel_err": float(e_lc.mean()),
+        "mlp_mean_rel_err": float(e_ml.mean()),
+        "mlp_used_frac": float(use.mean()),
+        "gate_min_live": int(gate.min_live),
+        "per_decade": [dict(d, mlp=m["mean_rel_err"]) for d, m in
+                       zip(learned.rel_err_table(te.cards, te.lc),
+                           learned.rel_err_table(te.cards, est))],
+        "dataset_s": t_gen,
+        "train_s": t_train,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +176,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the serving (config 4) and learned-estimator (config 5) legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -266,6 +338,21 @@ def main():
                                                          prof["scan_stats"][1] / 1e3)) / BW_s,
         }
         del probe
+
+    if not args.no_extras:
+        for name, fn in (("serving", lambda: serving_extra(pkts, log)),
+                         ("learned_vs_lc", lambda: learned_extra(log))):
+            t0 = time.perf_counter()
+            try:
+                out[name] = fn()
+            except Exception as e:  # report, keep the main line
+                out[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"{name} in {time.perf_counter() - t0:.1f} s")
+        if "serving" in out and "p99_latency_ms" in out["serving"]:
+            out["p99_latency_ms"] = out["serving"]["p99_latency_ms"]
+        if "learned_vs_lc" in out and "mlp_mean_rel_err" in out["learned_vs_lc"]:
+            out["learned_vs_lc_rel_err"] = [out["learned_vs_lc"]["mlp_mean_rel_err"],
+                                            out["learned_vs_lc"]["lc_mean_rel_err"]]
 
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

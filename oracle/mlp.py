@@ -1,10 +1,12 @@
 """fp64 oracle of the learned cardinality estimator -- TEST INFRASTRUCTURE ONLY.
 
 The paper has no learned part; this network is an addition of this project.  It maps the
-per-age live-cell counts of a host's union SLE (x_a for ages a < 10, divided by eta') to the
-natural log of the host's cardinality:
+per-age live-cell counts of a host's union SLE (x_a for ages a < 10) to the natural log of
+the host's cardinality.  Each count is encoded as the log of that age's own linear-counting
+estimate (Eq. 9 with eta' + 1 in the denominator so a full SLE stays finite), scaled by 1/8:
 
-    h1 = relu(W1 x + b1)      W1: 64 x 10
+    phi_a = log1p(-eta' * log1p(-x_a / (eta' + 1))) / 8
+    h1 = relu(W1 phi + b1)    W1: 64 x 10
     h2 = relu(W2 h1 + b2)     W2: 64 x 64
     y  = W3 h2 + b3           W3: 1 x 64
     loss = mean over the batch of (y - log c)^2
@@ -47,8 +49,14 @@ def unflatten(v: np.ndarray) -> dict:
     return p
 
 
+def encode(x: np.ndarray, etap: int) -> np.ndarray:
+    """Input encoding of per-age counts (fp64)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.log1p(-etap * np.log1p(-x / (etap + 1.0))) / 8.0
+
+
 def forward(p: dict, x: np.ndarray):
-    """x: (B, 10).  Returns (y (B,), cache)."""
+    """x: (B, 10) encoded inputs.  Returns (y (B,), cache)."""
     x = np.asarray(x, dtype=np.float64)
     z1 = x @ p["W1"].T + p["b1"]
     h1 = np.maximum(z1, 0.0)

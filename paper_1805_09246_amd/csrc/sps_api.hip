@@ -639,8 +639,8 @@ int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target
   const uint64_t w = sps::mlp_grad_waves((uint32_t)n);
   float* partial = static_cast<float*>(d_work);
   float* partial_loss = partial + w * SPS_MLP_PARAMS;
-  SPS_HIP(sps::launch_mlp_grad(d_w, d_feat, d_target, d_idx, (uint32_t)n, 1.f / (float)etap,
-                               partial, partial_loss, d_grad, d_loss, (hipStream_t)stream));
+  SPS_HIP(sps::launch_mlp_grad(d_w, d_feat, d_target, d_idx, (uint32_t)n, etap, partial,
+                               partial_loss, d_grad, d_loss, (hipStream_t)stream));
   return SPS_OK;
 }
 
@@ -655,7 +655,7 @@ int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32
 int sps_mlp_forward(const float* d_w, const uint32_t* d_feat, size_t n, uint32_t etap, int bf16,
                     float* d_y, void* stream) {
   if (!d_w || (n && (!d_feat || !d_y)) || n > 0xFFFFFFFFull || etap == 0) return SPS_EINVAL;
-  SPS_HIP(sps::launch_mlp_forward(d_w, d_feat, (uint32_t)n, 1.f / (float)etap, bf16, d_y,
+  SPS_HIP(sps::launch_mlp_forward(d_w, d_feat, (uint32_t)n, etap, bf16, d_y,
                                   device_cu_count(), (hipStream_t)stream));
   return SPS_OK;
 }

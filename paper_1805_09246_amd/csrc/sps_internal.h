@@ -63,6 +63,14 @@ __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
+// Input encoding of the learned estimator: the count x of live union-SLE cells at one age is
+// turned into the log of that age's own linear-counting estimate, scaled to about [0, 1]:
+// phi = log1p(-eta' log1p(-x / (eta' + 1))) / 8  (x <= eta', so the argument never reaches 1).
+__device__ __forceinline__ float mlp_encode(uint32_t x, uint32_t etap) {
+  const float u = (float)x / (float)(etap + 1u);
+  return log1pf(-(float)etap * log1pf(-u)) * 0.125f;
+}
+
 // Stage timing (sps_api.hip): brackets one launch with HIP events while profiling is on.
 class ProfScope {
  public:
@@ -111,11 +119,11 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
 // Learned estimator (sps_mlp.hip).
 uint32_t mlp_grad_waves(uint32_t n);
 hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* target,
-                           const uint32_t* idx, uint32_t n, float inv_norm, float* partial,
+                           const uint32_t* idx, uint32_t n, uint32_t etap, float* partial,
                            float* partial_loss, float* grad, float* loss, hipStream_t st);
 hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint32_t step,
                            float lr, float b1, float b2, float eps, hipStream_t st);
-hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, float inv_norm,
+hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, uint32_t etap,
                               int bf16, float* y, int n_cu, hipStream_t st);
 
 }  // namespace sps

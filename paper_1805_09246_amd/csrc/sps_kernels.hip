@@ -11,6 +11,7 @@
 namespace sps {
 
 constexpr int kWave = 64;
+constexpr uint32_t kJoinLdsMax = 64u << 10;  // hot bitmaps staged in LDS up to this size
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -208,8 +209,15 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
     const uint64_t nvec = d.row_stride / 8;
     const uint64_t step = (uint64_t)nb_row * blockDim.x;
     uint32_t cnt = 0;
-    for (uint64_t v = (uint64_t)chunk * blockDim.x + threadIdx.x; v < nvec; v += step)
-      cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
+    uint64_t v = (uint64_t)chunk * blockDim.x + threadIdx.x;
+    for (; v + 3 * step < nvec; v += 4 * step) {  // four independent loads in flight
+      const u32x4 a = __builtin_nontemporal_load(&rowp[v]);
+      const u32x4 b = __builtin_nontemporal_load(&rowp[v + step]);
+      const u32x4 c = __builtin_nontemporal_load(&rowp[v + 2 * step]);
+      const u32x4 e = __builtin_nontemporal_load(&rowp[v + 3 * step]);
+      cnt += live8(a, lo) + live8(b, lo) + live8(c, lo) + live8(e, lo);
+    }
+    for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
     cnt = wave_sum(cnt);
     if (lane_id() == 0) red[threadIdx.x / kWave] = cnt;
     __syncthreads();
@@ -249,75 +257,98 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
 
 __device__ __forceinline__ bool hot_bit(const uint32_t* __restrict__ hot, uint32_t q,
                                         uint32_t row, uint32_t col) {
-  const uint64_t bit = ((uint64_t)row << q) + col;
+  const uint32_t bit = (row << q) + col;
   return (hot[bit >> 5] >> (bit & 31u)) & 1u;
 }
 
-// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  One lane per pair (he0, he1) of
-// hot SREs of rows 0 and 1: B(1) = he0 ^ he1 gives address bits [0, q).  Row i >= 2 adds the
-// delta bits [(i-2)delta + q, (i-1)delta + q); its q bits B(i) = x >> ((i-1)delta) then
-// overlap B(i-1) by construction, and the tuple survives when SRE he0 ^ B(i) of row i is hot
-// and no bit at or above 32 is set.  The search is depth first over the 2^delta choices per
-// row; the partial address itself is the stack.  A full tuple is kept when RHFG[0] of the
-// address is he0.
+// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  Each lane owns pairs (he0, he1)
+// of hot SREs of rows 0 and 1 (pair p, p + stride, ...).  B(1) = he0 ^ he1 gives address
+// bits [0, q).  Row i >= 2 adds the delta bits [(i-2)delta + q, (i-1)delta + q); its q bits
+// B(i) = x >> ((i-1)delta) then overlap B(i-1) by construction, and the extension survives
+// when SRE he0 ^ B(i) of row i is hot and no bit at or above 32 is set.  The search is depth
+// first over the 2^delta extensions per row with the partial address itself as the stack.
+// A full tuple is kept when RHFG[0] of the address is he0.
+//
+// Lanes advance as a state machine, one bitmap probe per iteration: a lane whose search ends
+// takes its next pair at once, so a wave never waits for its slowest lane's search.  When
+// the hot bitmaps fit, the block stages them in LDS (kLds).
+template <bool kLds>
 __global__ void __launch_bounds__(256) k_join(Dev d) {
+  extern __shared__ uint32_t sh_hot[];
+  const uint32_t q = d.q, dl = d.delta, r = d.r;
+  const uint32_t* __restrict__ hot = d.hot;
+  if (kLds) {
+    const uint32_t words = (r << q) >> 5;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh_hot[w] = d.hot[w];
+    __syncthreads();
+    hot = sh_hot;
+  }
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
   const uint64_t pairs = (uint64_t)n0 * n1;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint32_t qmask = (1u << q) - 1u, dmask = (1u << dl) - 1u;
-  const uint32_t* __restrict__ hot = d.hot;
-  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs; p += stride) {
-    uint32_t a, bb;
-    if (pairs <= 0xFFFFFFFFull) {
-      a = (uint32_t)p / n1;
-      bb = (uint32_t)p - a * n1;
-    } else {
-      a = (uint32_t)(p / n1);
-      bb = (uint32_t)(p - (uint64_t)a * n1);
-    }
-    const uint32_t he0 = d.hse[a];
-    const uint32_t he1 = d.hse[(1ull << q) + bb];
-    uint64_t x = he0 ^ he1;  // bits [0, q)
-    uint32_t i = 2, t = 0;
-    for (;;) {
-      if (t <= dmask) {
-        const uint32_t sh = (i - 2) * dl + q;  // position of this row's new bits
-        const uint64_t xi = x | ((uint64_t)t << sh);
-        bool ok = (xi >> 32) == 0;
-        if (ok) {
-          const uint32_t Bi = (uint32_t)(xi >> ((i - 1) * dl)) & qmask;
-          ok = hot_bit(hot, q, i, he0 ^ Bi);
-        }
-        if (!ok) {
-          ++t;
-        } else if (i + 1 == r) {
-          const uint32_t addr = (uint32_t)xi;
-          if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
-            const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-            if (pos < d.cand_cap) d.cand[pos] = addr;
-          }
-          ++t;
-        } else {
-          x = xi;
-          ++i;
+  uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t he0 = 0, i = 2, t = 0;
+  uint64_t x = 0;
+  bool active = p < pairs;
+  if (active) {
+    const uint32_t a = (uint32_t)(p / n1), b = (uint32_t)(p - (uint64_t)a * n1);
+    he0 = d.hse[a];
+    x = he0 ^ d.hse[(1u << q) + b];
+  }
+  while (__ballot(active) != 0) {
+    if (!active) continue;
+    if (t > dmask) {  // row i exhausted: back up one row, or take the next pair
+      if (i == 2) {
+        p += stride;
+        active = p < pairs;
+        if (active) {
+          const uint32_t a = (uint32_t)(p / n1), b = (uint32_t)(p - (uint64_t)a * n1);
+          he0 = d.hse[a];
+          x = he0 ^ d.hse[(1u << q) + b];
           t = 0;
         }
       } else {
-        if (i == 2) break;
         --i;
         const uint32_t sh = (i - 2) * dl + q;
         t = (uint32_t)((x >> sh) & dmask) + 1u;
         x &= (1ull << sh) - 1ull;
       }
+      continue;
+    }
+    const uint32_t sh = (i - 2) * dl + q;  // position of this row's new bits
+    const uint64_t xi = x | ((uint64_t)t << sh);
+    bool ok = (xi >> 32) == 0;
+    if (ok) ok = hot_bit(hot, q, i, he0 ^ ((uint32_t)(xi >> ((i - 1) * dl)) & qmask));
+    if (ok && i + 1 == r) {
+      const uint32_t addr = (uint32_t)xi;
+      if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+        const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+        if (pos < d.cand_cap) d.cand[pos] = addr;
+      }
+      ++t;
+    } else if (ok) {
+      x = xi;
+      ++i;
+      t = 0;
+    } else {
+      ++t;
     }
   }
 }
 
 // Union SLE of host x (Alg. 8): cell z keeps the smallest stamp over the r' rows, i.e. the
-// largest distance, so it is live only when live in every row.  Lane l handles cells
-// l, l + 64, ...; counts of live cells per age come from wave ballots, and lane a ends up
-// holding x_a (cells with stamp >= max(1, cur - a)) for a < nfeat.
+// largest distance, so it is live only when live in every row.  When SLEs start on 8-cell
+// boundaries each lane takes 8 consecutive cells per pass (one 16-byte load per row, all
+// rows' loads in flight together); otherwise one cell per lane.  Per-lane counts are summed
+// over the wave once at the end; lane a ends up holding x_a (cells with stamp >=
+// max(1, cur - a)) for a < nfeat, and every lane holds |USLE|^k in `live`.
+__device__ __forceinline__ uint32_t min_u16_pair(uint32_t a, uint32_t b, int hi) {
+  const uint32_t x = hi ? a >> 16 : a & 0xFFFFu;
+  const uint32_t y = hi ? b >> 16 : b & 0xFFFFu;
+  return x < y ? x : y;
+}
+
 __device__ __forceinline__ void usle_counts(const Dev& d, uint32_t x, uint32_t cur, uint32_t lo,
                                             uint32_t nfeat, uint32_t& live, uint32_t& feat) {
   uint64_t base[kMaxRP];
@@ -325,27 +356,66 @@ __device__ __forceinline__ void usle_counts(const Dev& d, uint32_t x, uint32_t c
 #pragma unroll
   for (int i = 0; i < kMaxRP; ++i)
     base[i] = (uint64_t)i * d.row_stride + (uint64_t)(fmix32(x ^ d.seed_lh[i]) & qpmask) * d.deltap;
-  live = 0;
-  feat = 0;
   const uint32_t lane = lane_id();
-  for (uint32_t z0 = 0; z0 < d.etap; z0 += kWave) {
-    const uint32_t z = z0 + lane;
-    uint32_t m = 0;
-    if (z < d.etap) {
-      m = 0xFFFFu;
+  uint32_t c_live = 0, c_age[32];
+  for (uint32_t a = 0; a < 32; ++a) c_age[a] = 0;
+  const bool vec = ((d.deltap & 7u) == 0) && ((d.etap & 7u) == 0);  // uniform
+  if (vec) {
+    for (uint32_t z0 = 0; z0 < d.etap; z0 += 8 * kWave) {
+      const uint32_t z = z0 + lane * 8;
+      if (z < d.etap) {
+        u32x4 v[kMaxRP];
 #pragma unroll
-      for (int i = 0; i < kMaxRP; ++i)
-        if (i < (int)d.rp) {
-          const uint32_t v = d.slea[base[i] + z];
-          m = v < m ? v : m;
+        for (int i = 0; i < kMaxRP; ++i)
+          if (i < (int)d.rp) v[i] = *reinterpret_cast<const u32x4*>(d.slea + base[i] + z);
+        uint32_t m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = 0xFFFFu;
+#pragma unroll
+        for (int i = 0; i < kMaxRP; ++i) {
+          if (i < (int)d.rp) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint32_t w = k < 2 ? v[i].x : (k < 4 ? v[i].y : (k < 6 ? v[i].z : v[i].w));
+              const uint32_t c = (k & 1) ? w >> 16 : w & 0xFFFFu;
+              m[k] = c < m[k] ? c : m[k];
+            }
+          }
         }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          c_live += m[k] >= lo;  // lo >= 1, so never-written cells are not live
+          for (uint32_t a = 0; a < nfeat; ++a) {
+            const uint32_t lo_a = cur > a + 1u ? cur - a : 1u;
+            c_age[a] += m[k] >= lo_a;
+          }
+        }
+      }
     }
-    live += (uint32_t)__popcll(__ballot(m >= lo && m != 0u));
-    for (uint32_t a = 0; a < nfeat; ++a) {
-      const uint32_t lo_a = cur > a + 1u ? cur - a : 1u;
-      const uint32_t c = (uint32_t)__popcll(__ballot(m >= lo_a));
-      if (lane == a) feat += c;
+  } else {
+    for (uint32_t z0 = 0; z0 < d.etap; z0 += kWave) {
+      const uint32_t z = z0 + lane;
+      if (z < d.etap) {
+        uint32_t m = 0xFFFFu;
+#pragma unroll
+        for (int i = 0; i < kMaxRP; ++i)
+          if (i < (int)d.rp) {
+            const uint32_t v = d.slea[base[i] + z];
+            m = v < m ? v : m;
+          }
+        c_live += m >= lo;
+        for (uint32_t a = 0; a < nfeat; ++a) {
+          const uint32_t lo_a = cur > a + 1u ? cur - a : 1u;
+          c_age[a] += m >= lo_a;
+        }
+      }
     }
+  }
+  live = wave_sum(c_live);
+  feat = 0;
+  for (uint32_t a = 0; a < nfeat; ++a) {
+    const uint32_t t = wave_sum(c_age[a]);
+    if (lane == a) feat = t;
   }
 }
 
@@ -359,6 +429,7 @@ __device__ __forceinline__ float to_bf16(float f) {
 }
 
 __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
+  // in_lane: encoded feature of lane k (k < 10)
   const uint32_t lane = lane_id();
   const float* W1 = w;
   const float* b1 = W1 + SPS_MLP_HIDDEN * SPS_MLP_IN;
@@ -423,7 +494,7 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       const bool in_range = lane >= SPS_MLP_IN || (f >= mlp.lo[lane] && f <= mlp.hi[lane]);
       const bool all_in = __ballot(!in_range) == 0;
       const bool informative = __shfl(feat, 0, kWave) < d.etap - 1u;
-      const float y = mlp_forward_wave(mlp.w, f);
+      const float y = mlp_forward_wave(mlp.w, lane < SPS_MLP_IN ? mlp_encode(feat, d.etap) : 0.f);
       if (U >= mlp.min_live && all_in && informative && y >= 0.f && y <= mlp.log_max) {
         est = (double)expf(y);
         flags |= SPS_F_MLP;
@@ -451,21 +522,25 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
 
 // Stage 4: order the kept hosts ascending.  Hosts are distinct, so a host's rank is the
 // number of smaller kept hosts; every lane counts for one host over LDS tiles of the list.
-__global__ void __launch_bounds__(256) k_rank_sort(Dev d, sps_result* __restrict__ out,
-                                                   uint32_t cap, uint32_t* __restrict__ info) {
-  __shared__ uint32_t tile[1024];
+constexpr int kSortThreads = 1024;
+constexpr int kSortTile = 4096;
+
+__global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
+                                                            uint32_t cap,
+                                                            uint32_t* __restrict__ info) {
+  __shared__ uint32_t tile[kSortTile];
   const uint32_t n = min(d.ctrl->n_kept, d.cand_cap);
-  const uint32_t gsz = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gsz) {
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     const uint32_t h = i < n ? d.kept[i].host : 0u;
     uint32_t rank = 0;
-    for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
+    for (uint32_t t0 = 0; t0 < n; t0 += kSortTile) {
       __syncthreads();
-      for (uint32_t j = threadIdx.x; j < 1024 && t0 + j < n; j += blockDim.x)
+      for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile && t0 + j < n; j += blockDim.x)
         tile[j] = d.kept[t0 + j].host;
       __syncthreads();
-      const uint32_t m = n - t0 < 1024u ? n - t0 : 1024u;
+      const uint32_t m = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
+#pragma unroll 8
       for (uint32_t j = 0; j < m; ++j) rank += tile[j] < h;
     }
     if (i < n && rank < cap) out[rank] = d.kept[i];
@@ -505,7 +580,11 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
-    hipLaunchKernelGGL(k_join, dim3(n_cu * 4), dim3(256), 0, st, d);
+    const uint32_t lds_bytes = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
+    if (lds_bytes <= kJoinLdsMax)
+      hipLaunchKernelGGL(k_join<true>, dim3(n_cu * 4), dim3(256), lds_bytes, st, d);
+    else
+      hipLaunchKernelGGL(k_join<false>, dim3(n_cu * 4), dim3(256), 0, st, d);
   }
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
@@ -514,7 +593,7 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   }
   {
     ProfScope ps(SPS_STAGE_SORT, st);
-    hipLaunchKernelGGL(k_rank_sort, dim3(n_cu), dim3(256), 0, st, d, out, cap, info);
+    hipLaunchKernelGGL(k_rank_sort, dim3(32), dim3(kSortThreads), 0, st, d, out, cap, info);
   }
   return hipGetLastError();
 }
@@ -594,7 +673,16 @@ __global__ void __launch_bounds__(256) k_probe_stream(const u32x4* __restrict__ 
                                                       uint64_t nvec, uint32_t* sum) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t acc = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < nvec; i += 4 * stride) {
+    const u32x4 a = __builtin_nontemporal_load(&buf[i]);
+    const u32x4 b = __builtin_nontemporal_load(&buf[i + stride]);
+    const u32x4 c = __builtin_nontemporal_load(&buf[i + 2 * stride]);
+    const u32x4 e = __builtin_nontemporal_load(&buf[i + 3 * stride]);
+    acc += (a.x ^ a.y ^ a.z ^ a.w) + (b.x ^ b.y ^ b.z ^ b.w) + (c.x ^ c.y ^ c.z ^ c.w) +
+           (e.x ^ e.y ^ e.z ^ e.w);
+  }
+  for (; i < nvec; i += stride) {
     const u32x4 v = __builtin_nontemporal_load(&buf[i]);
     acc += v.x ^ v.y ^ v.z ^ v.w;
   }

@@ -1,8 +1,8 @@
 // sps_mlp.hip -- learned cardinality estimator: training and batched inference kernels.
 //
 // Network (an addition to the paper's method): per-age live counts x_a of a host's union SLE
-// (a < 10, divided by eta') -> 64 ReLU -> 64 ReLU -> 1, predicting the natural log of the
-// host's cardinality.  Parameters are float32 in the order W1 (64 x 10), b1, W2 (64 x 64),
+// (a < 10, each encoded by mlp_encode) -> 64 ReLU -> 64 ReLU -> 1, predicting the natural
+// log of the host's cardinality.  Parameters are float32 in the order W1 (64 x 10), b1, W2 (64 x 64),
 // b2, W3 (1 x 64), b3.  Loss: mean squared error over the batch.
 //
 // Layout on the GPU: one wave64 per sample, hidden unit j in lane j.  A wave keeps its
@@ -41,12 +41,12 @@ __device__ __forceinline__ float round_bf16(float f) {
 }  // namespace
 
 // Partial gradients of the loss over samples idx[0..n) (or 0..n when idx is null).
-// inv_norm = 1/eta' (features are counts); scale = 2 / (batch size) for the mean.
+// Features are counts out of etap cells; scale = 2 / (batch size) for the mean.
 __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ w,
                                                   const uint32_t* __restrict__ feat,
                                                   const float* __restrict__ target,
                                                   const uint32_t* __restrict__ idx, uint32_t n,
-                                                  float inv_norm, float scale,
+                                                  uint32_t etap, float scale,
                                                   float* __restrict__ partial,
                                                   float* __restrict__ partial_loss) {
   const int lane = (int)__lane_id();
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ w,
   for (uint32_t s = wave; s < n; s += n_waves) {
     const uint32_t row = idx ? idx[s] : s;
     float x[kIn];
-    for (int i = 0; i < kIn; ++i) x[i] = (float)feat[(uint64_t)row * kIn + i] * inv_norm;
+    for (int i = 0; i < kIn; ++i) x[i] = mlp_encode(feat[(uint64_t)row * kIn + i], etap);
     const float t = target[row];
     // forward
     float z1 = b1;
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float* __restrict__ w, float* 
 // bfloat16 with float accumulation (the precision used inside scans).
 __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ w,
                                                      const uint32_t* __restrict__ feat,
-                                                     uint32_t n, float inv_norm, int bf16,
+                                                     uint32_t n, uint32_t etap, int bf16,
                                                      float* __restrict__ y_out) {
   const int lane = (int)__lane_id();
   const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ w
   const float b1 = w[oB1 + lane], b2 = w[oB2 + lane], w3 = R(w[oW3 + lane]), b3 = w[oB3];
   for (uint32_t s = wave; s < n; s += n_waves) {
     float z1 = 0.f;
-    for (int i = 0; i < kIn; ++i) z1 += w1[i] * R((float)feat[(uint64_t)s * kIn + i] * inv_norm);
+    for (int i = 0; i < kIn; ++i) z1 += w1[i] * R(mlp_encode(feat[(uint64_t)s * kIn + i], etap));
     const float h1 = R(fmaxf(z1 + b1, 0.f));
     float z2 = 0.f;
     for (int k = 0; k < kH; ++k) z2 += w2row[k] * bcast(h1, k);
@@ -179,13 +179,13 @@ uint32_t mlp_grad_waves(uint32_t n) {
 }
 
 hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* target,
-                           const uint32_t* idx, uint32_t n, float inv_norm, float* partial,
+                           const uint32_t* idx, uint32_t n, uint32_t etap, float* partial,
                            float* partial_loss, float* grad, float* loss, hipStream_t st) {
   const uint32_t waves = mlp_grad_waves(n);
   {
     ProfScope ps(SPS_STAGE_MLP, st);
     hipLaunchKernelGGL(k_mlp_grad, dim3(waves / 4), dim3(256), 0, st, w, feat, target, idx, n,
-                       inv_norm, 2.f / (float)n, partial, partial_loss);
+                       etap, 2.f / (float)n, partial, partial_loss);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kP + 255) / 256), dim3(256), 0, st, partial,
                        partial_loss, waves, 1.f / (float)n, grad, loss);
   }
@@ -202,14 +202,13 @@ hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, float inv_norm,
+hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, uint32_t etap,
                               int bf16, float* y, int n_cu, hipStream_t st) {
   if (n == 0) return hipSuccess;
   uint32_t blocks = (n + 3) / 4;
   if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
   ProfScope ps(SPS_STAGE_MLP, st);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, st, w, feat, n, inv_norm, bf16,
-                     y);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, st, w, feat, n, etap, bf16, y);
   return hipGetLastError();
 }
 

@@ -35,23 +35,33 @@ class Dataset:
     etap: int
 
 
-def generate(params: dict, n_hosts: int, seed: int, n_backgrounds: int = 4,
-             hosts_per_stream: int = 150, peer_budget: int = 16_000_000, log=None) -> Dataset:
-    """Hosts with log-uniform cardinalities embedded into background streams, ingested by the
-    GPU sketch; per-age features and linear-counting estimates read back per host."""
+def make_backgrounds(params: dict, seed: int, n: int = 4) -> list:
+    """Sketches of n background streams (one window each) to embed hosts into."""
     from synth import make_stream
     from synth import learned as L
-
-    cards = L.draw_cards(seed, n_hosts)
-    hosts = L.host_addrs((seed % 97) * 10_000_000, n_hosts)
-    salts = L.peer_salts(seed, n_hosts)
     bases = []
-    for b in range(n_backgrounds):
+    for b in range(n):
         st = make_stream(L.background_recipe(seed * 131 + b))
         sk = sps.Sketch(params)
         for s in range(1, WINDOW + 1):
             sk.ingest(torch.from_numpy(st.slice_pkts(s).view(np.int32)).cuda(), s)
         bases.append(sk)
+    return bases
+
+
+def generate(params: dict, n_hosts: int, seed: int, bases: list | None = None,
+             hosts_per_stream: int = 150, peer_budget: int = 16_000_000, log=None) -> Dataset:
+    """Hosts with log-uniform cardinalities embedded into background streams, ingested by the
+    GPU sketch; per-age features and linear-counting estimates read back per host."""
+    from synth import learned as L
+
+    cards = L.draw_cards(seed, n_hosts)
+    hosts = L.host_addrs((seed % 97) * 10_000_000, n_hosts)
+    salts = L.peer_salts(seed, n_hosts)
+    own = bases is None
+    if own:
+        bases = make_backgrounds(params, seed)
+    n_backgrounds = len(bases)
     # streams: consecutive hosts up to hosts_per_stream and the peer budget
     chunks, a = [], 0
     while a < n_hosts:
@@ -80,8 +90,9 @@ def generate(params: dict, n_hosts: int, seed: int, n_backgrounds: int = 4,
             log(f"dataset {seed:#x}: stream {k + 1}/{len(chunks)}")
     torch.cuda.synchronize()
     r = sps.results_to_numpy(res, n_hosts)
-    for s in bases:
-        s.close()
+    if own:
+        for s in bases:
+            s.close()
     work.close()
     return Dataset(feats.cpu().numpy().view(np.uint32), cards, r["estimate"].copy(),
                    r["flags"].copy(), params["etap"])
@@ -100,12 +111,20 @@ def init_weights(seed: int) -> np.ndarray:
     return w
 
 
+def informative(ds: Dataset) -> np.ndarray:
+    """Hosts whose newest age is not saturated: the only ones the network may estimate."""
+    return ds.features[:, 0] < ds.etap - 1
+
+
 def train(ds: Dataset, epochs: int = 30, batch: int = 4096, lr: float = 3e-3, seed: int = 1,
           log=None) -> torch.Tensor:
-    """Adam on the mean squared error of log-cardinality; returns device float32 weights."""
-    n = ds.features.shape[0]
-    feat = torch.from_numpy(np.ascontiguousarray(ds.features).view(np.int32)).cuda()
-    target = torch.from_numpy(np.log(ds.cards.astype(np.float64)).astype(np.float32)).cuda()
+    """Adam on the mean squared error of log-cardinality over the informative hosts; returns
+    device float32 weights."""
+    keep = informative(ds)
+    feats = np.ascontiguousarray(ds.features[keep])
+    n = feats.shape[0]
+    feat = torch.from_numpy(feats.view(np.int32)).cuda()
+    target = torch.from_numpy(np.log(ds.cards[keep].astype(np.float64)).astype(np.float32)).cuda()
     w = torch.from_numpy(init_weights(seed)).cuda()
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
@@ -153,8 +172,7 @@ def gated(ds: Dataset, y: np.ndarray, gate: Gate) -> tuple:
     """Estimates the scan would report with the network attached (mirrors the kernel's rule)."""
     f = ds.features.astype(np.float32) / np.float32(ds.etap)
     in_range = np.all((f >= gate.lo) & (f <= gate.hi), axis=1)
-    informative = ds.features[:, 0] < ds.etap - 1
-    use = (ds.features[:, -1] >= gate.min_live) & in_range & informative & \
+    use = (ds.features[:, -1] >= gate.min_live) & in_range & informative(ds) & \
         (y >= 0) & (y <= math.log(gate.max_card))
     return np.where(use, np.exp(y), ds.lc), use
 
@@ -162,7 +180,7 @@ def gated(ds: Dataset, y: np.ndarray, gate: Gate) -> tuple:
 def fit_gate(train_ds: Dataset, val: Dataset, y_val: np.ndarray, max_card: float = 1e6) -> Gate:
     """Feature ranges from the training set; min_live chosen on the validation set to minimise
     the mean relative error."""
-    f = train_ds.features.astype(np.float32) / np.float32(train_ds.etap)
+    f = train_ds.features[informative(train_ds)].astype(np.float32) / np.float32(train_ds.etap)
     lo, hi = f.min(0), f.max(0)
     best = None
     for ml in [0, 64, 128, 256, 384, 512, 640, 768, 832, 896, 960, 992, 1008, 1016, 1020, 1023,

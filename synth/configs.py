@@ -64,3 +64,17 @@ C3_WINDOW, C3_THRESHOLD = 10, 2048.0
 C3_SMALL_RECIPE = MultiRecipe(name="c3_shape_small", seed=0x180509246013, n_routers=16,
                               median=1 << 17, sigma=1.0, n_slices=12, window=10,
                               n_hosts=1 << 20, zipf_s=1.05, planted=[3000, 8000, 20000, 60000])
+
+# Serving loop: 64 routers, Poisson batch arrivals at 2e9 packets/s (batches 4 Ki..4 Mi),
+# 120 slices of 10 ms, window 10, threshold 1024; all sketches resident (12 GiB budget).
+C4_PARAMS = sketch_params(q=14, r=11, delta=2, eta=8, qp=14, rp=5, etap=1024, deltap=1024,
+                          theta=1024, seed=0x5A5A180509246004)
+C4_WINDOW, C4_THRESHOLD = 10, 1024.0
+C4_ROUTERS, C4_RATE, C4_SLICE_S, C4_SLICES, C4_BUDGET = 64, 2e9, 0.010, 120, 12 << 30
+C4_SEED = 0x180509246004
+
+# Learned estimator: 1e6 training hosts, window 10, SLE array 5 x 65536 x 1024.
+C5_PARAMS = sketch_params(q=14, r=11, delta=2, eta=8, qp=16, rp=5, etap=1024, deltap=1024,
+                          theta=1024, seed=0x5A5A180509246005)
+C5_TRAIN, C5_VAL, C5_TEST = 1_000_000, 50_000, 100_000
+C5_SEEDS = (0x180509246005, 0x180509246015, 0x180509246025)

@@ -37,7 +37,7 @@ def test_forward_fp32_and_bf16():
     rng = np.random.default_rng(0)
     p = _params_np(3)
     x = _feat(rng, 3000)
-    want, _ = omlp.forward(p, x / ETAP)
+    want, _ = omlp.forward(p, omlp.encode(x, ETAP))
     w = _dev(omlp.flatten(p).astype(np.float32))
     xd = torch.from_numpy(x.view(np.int32)).cuda()
     y = torch.zeros(3000, dtype=torch.float32, device="cuda")
@@ -57,7 +57,7 @@ def test_gradient_against_fp64(n):
     x = _feat(rng, n + 11)
     t = rng.uniform(0, 12, n + 11)
     idx = rng.permutation(n + 11)[:n].astype(np.int32)
-    loss_ref, g_ref = omlp.loss_and_grad(p, x[idx] / ETAP, t[idx])
+    loss_ref, g_ref = omlp.loss_and_grad(p, omlp.encode(x[idx], ETAP), t[idx])
     gv = omlp.flatten(g_ref)
     w = _dev(omlp.flatten(p).astype(np.float32))
     xd = torch.from_numpy(x.view(np.int32)).cuda()
@@ -96,10 +96,12 @@ def test_adam_step_against_fp64():
     du_ref = omlp.flatten(p1) - omlp.flatten(p)
     tol = 1e-4 * np.abs(du_ref) + 2 * np.finfo(np.float32).eps * np.abs(w0)
     assert np.all(np.abs(du - du_ref) <= tol)
-    for got, want in ((md, m1), (vd, v1)):
+    # moments: relative to the size of the terms they sum (m may cancel to near zero)
+    gf, mf, vf = omlp.flatten(g), omlp.flatten(m), omlp.flatten(v)
+    for got, want, scale in ((md, m1, 0.9 * np.abs(mf) + 0.1 * np.abs(gf)),
+                             (vd, v1, 0.999 * vf + 0.001 * gf * gf)):
         a = got.cpu().numpy().astype(np.float64)
-        b = omlp.flatten(want)
-        assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-12)) <= 1e-5
+        assert np.all(np.abs(a - omlp.flatten(want)) <= 1e-5 * scale + 1e-30)
 
 
 def test_generator_matches_cpu_twin():
@@ -161,9 +163,10 @@ def test_trained_network_beats_linear_counting():
     counting saturates."""
     from synth.configs import C2_PARAMS
     params = dict(C2_PARAMS)
-    tr = learned.generate(params, 60000, seed=0x5EED01, log=print)
-    va = learned.generate(params, 10000, seed=0x5EED02, log=print)
-    te = learned.generate(params, 20000, seed=0x5EED03, log=print)
+    bases = learned.make_backgrounds(params, 0x5EED00, n=2)
+    tr = learned.generate(params, 60000, seed=0x5EED01, bases=bases, log=print)
+    va = learned.generate(params, 10000, seed=0x5EED02, bases=bases, log=print)
+    te = learned.generate(params, 20000, seed=0x5EED03, bases=bases, log=print)
     w = learned.train(tr, epochs=25, batch=2048, lr=3e-3, log=print)
     gate = learned.fit_gate(tr, va, learned.predict(w, va))
     est, use = learned.gated(te, learned.predict(w, te), gate)
