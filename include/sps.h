@@ -64,8 +64,8 @@ typedef struct sps_pkt {
 
 /* Sketch shape.  Notation of the paper:
  *   SRE array (Sec. 3.3): r rows x 2^q SREs, eta u16 cells per SRE, RHFG shift step delta.
- *     Requires 3 <= r <= 32, 1 <= delta < q <= 24, (r-2)*delta + q >= 32 (every address bit
- *     is recovered, Eq. 6-7), (r-2)*delta <= 31, eta in {8, 16, 32, 64}.
+ *     Requires 3 <= r <= 32, 6 <= q <= 24, 1 <= delta <= 5, delta < q, (r-2)*delta + q >= 32
+ *     (every address bit is recovered, Eq. 6-7), (r-2)*delta <= 31, eta in {8, 16, 32, 64}.
  *   SLE array (Sec. 4): r' rows x 2^q' SLEs, eta' cells per SLE, adjacent SLEs offset by
  *     delta' cells (a row holds 2^q' * delta' + eta' - delta' cells).  Requires
  *     1 <= q' <= 26, 1 <= r' <= 8, eta' a power of two in [16, 65536], delta' a power of
@@ -236,7 +236,7 @@ int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target
 /* One Adam step (Kingma & Ba 2015, bias-corrected; step counts from 1) on d_w with moment
  * buffers d_m, d_v (SPS_MLP_PARAMS floats each). */
 int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32_t step,
-                 float lr, float beta1, float beta2, float eps, void* stream);
+                 float lr, double beta1, double beta2, float eps, void* stream);
 
 /* Batched inference: d_y[s] = predicted log cardinality of feature row s (n rows of 10 u32
  * counts).  bf16 != 0 uses the scan's precision (bfloat16 weights and activations, float32

@@ -67,7 +67,7 @@ uint32_t effective_cand_cap(const sps_params* p) { return p->cand_cap ? p->cand_
 int validate(const sps_params* p) {
   if (!p) return SPS_EINVAL;
   if (p->q < 6 || p->q > 24 || p->r < 3 || p->r > (uint32_t)sps::kMaxR) return SPS_EINVAL;
-  if (p->delta < 1 || p->delta >= p->q) return SPS_EINVAL;
+  if (p->delta < 1 || p->delta > 5 || p->delta >= p->q) return SPS_EINVAL;
   if ((uint64_t)(p->r - 2) * p->delta + p->q < 32) return SPS_EINVAL;  // every bit recovered
   if ((uint64_t)(p->r - 2) * p->delta > 31) return SPS_EINVAL;
   if (!(p->eta == 8 || p->eta == 16 || p->eta == 32 || p->eta == 64)) return SPS_EINVAL;
@@ -103,7 +103,7 @@ uint64_t splitmix64_next(uint64_t& st) {
 }
 
 struct Layout {
-  uint64_t ctrl, info, sre, slea, hot, hse, cand, kept, sorted, total;
+  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, total;
   uint64_t row_len, row_stride, sre_cells, slea_cells;
 };
 
@@ -120,6 +120,7 @@ Layout layout_of(const sps_params* p) {
   L.sre = o;    o += round_up(L.sre_cells * 2, 256);
   L.slea = o;   o += round_up(L.slea_cells * 2, 256);
   L.hot = o;    o += round_up(((uint64_t)p->r << p->q) / 8, 256);
+  L.hot_t = o;  o += round_up(((uint64_t)p->r << p->q) / 8, 256);
   L.hse = o;    o += round_up(((uint64_t)2 << p->q) * 4, 256);
   L.cand = o;   o += round_up(cap * 4, 256);
   L.kept = o;   o += round_up(cap * sizeof(sps_result), 256);
@@ -301,6 +302,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.sre = reinterpret_cast<uint16_t*>(b + L.sre);
   d.slea = reinterpret_cast<uint16_t*>(b + L.slea);
   d.hot = reinterpret_cast<uint32_t*>(b + L.hot);
+  d.hot_t = reinterpret_cast<uint32_t*>(b + L.hot_t);
   d.hse = reinterpret_cast<uint32_t*>(b + L.hse);
   d.cand = reinterpret_cast<uint32_t*>(b + L.cand);
   d.kept = reinterpret_cast<sps_result*>(b + L.kept);
@@ -645,7 +647,7 @@ int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target
 }
 
 int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32_t step,
-                 float lr, float beta1, float beta2, float eps, void* stream) {
+                 float lr, double beta1, double beta2, float eps, void* stream) {
   if (!d_w || !d_m || !d_v || !d_grad || step == 0) return SPS_EINVAL;
   SPS_HIP(sps::launch_mlp_adam(d_w, d_m, d_v, d_grad, step, lr, beta1, beta2, eps,
                                (hipStream_t)stream));

@@ -19,7 +19,8 @@ struct Ctrl {
   uint32_t hse_count[2];      // hot SREs found in rows 0 and 1
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
   uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
-  uint32_t pad[64 - kMaxRP - 4];
+  unsigned long long join_next;  // next (he0, he1) pair handed out by the join
+  uint32_t pad[64 - kMaxRP - 4 - 2];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte block");
 
@@ -37,6 +38,8 @@ struct Dev {
   uint16_t* sre;          // [r][2^q][eta]
   uint16_t* slea;         // [r'][row_stride], cells >= row_len are padding (always 0)
   uint32_t* hot;          // [r][2^q / 32] hot-SRE bitmap
+  uint32_t* hot_t;        // [r][2^q / 32] the same bits transposed for the join: bit
+                          // (low << delta) + top of row i is hot_i[low | top << (q - delta)]
   uint32_t* hse;          // [2][2^q] hot-SRE column lists of rows 0 and 1
   uint32_t* cand;         // [cand_cap] recovered candidates
   sps_result* kept;       // [cand_cap] kept hosts, unordered
@@ -122,7 +125,7 @@ hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* ta
                            const uint32_t* idx, uint32_t n, uint32_t etap, float* partial,
                            float* partial_loss, float* grad, float* loss, hipStream_t st);
 hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint32_t step,
-                           float lr, float b1, float b2, float eps, hipStream_t st);
+                           float lr, double b1, double b2, float eps, hipStream_t st);
 hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, uint32_t etap,
                               int bf16, float* y, int n_cu, hipStream_t st);
 

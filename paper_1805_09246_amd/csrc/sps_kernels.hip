@@ -176,9 +176,23 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
 // ---------------------------------------------------------------------------------------
 // Scan.
 // ---------------------------------------------------------------------------------------
-__global__ void k_scan_reset(Ctrl* c) {
-  uint32_t* w = reinterpret_cast<uint32_t*>(c);
-  for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
+__global__ void __launch_bounds__(256) k_scan_reset(Ctrl* c, uint32_t* hot_t, uint32_t words) {
+  if (blockIdx.x == 0) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(c);
+    for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+    hot_t[i] = 0;
+}
+
+hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st) {
+  const uint32_t words = with_table ? (uint32_t)(((uint64_t)d.r << d.q) >> 5) : 0u;
+  uint32_t blocks = (words + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  ProfScope ps(SPS_STAGE_SCAN_RESET, st);
+  hipLaunchKernelGGL(k_scan_reset, dim3(blocks), dim3(256), 0, st, d.ctrl, d.hot_t, words);
+  return hipGetLastError();
 }
 
 // number of the 8 u16 stamps in v that are >= lo
@@ -243,6 +257,12 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
     hw[0] = (uint32_t)mask;
     hw[1] = (uint32_t)(mask >> 32);
   }
+  if (hot) {  // the join's layout: all 2^delta extensions of a node in one entry
+    const uint32_t low = col & ((1u << (d.q - d.delta)) - 1u);
+    const uint32_t top = col >> (d.q - d.delta);
+    const uint32_t pos = (row << d.q) + (low << d.delta) + top;
+    atomicOr(&d.hot_t[pos >> 5], 1u << (pos & 31u));
+  }
   if (row < 2 && mask != 0) {
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(&d.ctrl->hse_count[row], (uint32_t)__popcll(mask));
@@ -255,84 +275,147 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
   }
 }
 
-__device__ __forceinline__ bool hot_bit(const uint32_t* __restrict__ hot, uint32_t q,
-                                        uint32_t row, uint32_t col) {
-  const uint32_t bit = (row << q) + col;
-  return (hot[bit >> 5] >> (bit & 31u)) & 1u;
+// Hot extensions of a node (Alg. 4-5 check, in bulk): bit t of the result says whether SRE
+// he0 ^ B(i) of row i is hot for the extension t, where B(i)'s low q-delta bits are `low`
+// xor he0's (already folded into `low`) and its top delta bits are t xor he0's top bits.
+// The transposed table holds, for each (row, low), the 2^delta bits over the top bits; the
+// xor with he0's top bits permutes them (swap blocks of 2^b bits for every set bit b).
+__device__ __forceinline__ uint32_t child_mask(const uint32_t* __restrict__ tb, uint32_t q,
+                                               uint32_t dl, uint32_t row, uint32_t low,
+                                               uint32_t top0) {
+  const uint32_t pos = (row << q) + (low << dl);
+  const uint32_t width = 1u << dl;
+  const uint32_t wmask = width == 32u ? 0xFFFFFFFFu : ((1u << width) - 1u);
+  uint32_t m = (tb[pos >> 5] >> (pos & 31u)) & wmask;
+  if (top0 & 1u) m = ((m >> 1) & 0x55555555u) | ((m & 0x55555555u) << 1);
+  if (top0 & 2u) m = ((m >> 2) & 0x33333333u) | ((m & 0x33333333u) << 2);
+  if (top0 & 4u) m = ((m >> 4) & 0x0F0F0F0Fu) | ((m & 0x0F0F0F0Fu) << 4);
+  if (top0 & 8u) m = ((m >> 8) & 0x00FF00FFu) | ((m & 0x00FF00FFu) << 8);
+  if (top0 & 16u) m = (m >> 16) | (m << 16);
+  return m & wmask;
 }
 
-// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  Each lane owns pairs (he0, he1)
-// of hot SREs of rows 0 and 1 (pair p, p + stride, ...).  B(1) = he0 ^ he1 gives address
-// bits [0, q).  Row i >= 2 adds the delta bits [(i-2)delta + q, (i-1)delta + q); its q bits
-// B(i) = x >> ((i-1)delta) then overlap B(i-1) by construction, and the extension survives
-// when SRE he0 ^ B(i) of row i is hot and no bit at or above 32 is set.  The search is depth
-// first over the 2^delta extensions per row with the partial address itself as the stack.
-// A full tuple is kept when RHFG[0] of the address is he0.
+// Extensions t of row i whose bits stay below bit 32 (bit positions [(i-2)delta + q, ...)).
+__device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i) {
+  const uint32_t sh = (i - 2u) * dl + q;
+  const uint32_t width = 1u << dl;
+  if (sh >= 32u) return 1u;
+  const uint32_t free_bits = 32u - sh;
+  if (free_bits >= dl) return width == 32u ? 0xFFFFFFFFu : ((1u << width) - 1u);
+  return (1u << (1u << free_bits)) - 1u;
+}
+
+// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  A pair (he0, he1) of hot SREs of
+// rows 0 and 1 fixes B(1) = he0 ^ he1, the address bits [0, q).  Row i >= 2 adds the delta
+// bits [(i-2)delta + q, (i-1)delta + q); the overlap of B(i) with B(i-1) holds by
+// construction, so an extension survives when SRE he0 ^ B(i) of row i is hot and no bit at
+// or above 32 is set.  Each node's surviving extensions come from one load of the
+// transposed hot table.  The search is depth first with the partial address as the stack
+// (backing up re-reads the parent's extensions above the child taken).  A full tuple is
+// kept when RHFG[0] of the address is he0.
 //
-// Lanes advance as a state machine, one bitmap probe per iteration: a lane whose search ends
-// takes its next pair at once, so a wave never waits for its slowest lane's search.  When
-// the hot bitmaps fit, the block stages them in LDS (kLds).
-template <bool kLds>
-__global__ void __launch_bounds__(256) k_join(Dev d) {
-  extern __shared__ uint32_t sh_hot[];
+// Work: pairs are handed to waves in chunks from a global counter; inside a wave, lanes
+// whose search ended take the next pairs of the wave's chunk at once (ballot + mbcnt), so
+// lanes stay busy and waves stay balanced.  Every iteration a lane expands one node, backs
+// up one row, or takes a pair.  Tables and hot lists are staged in LDS when they fit.
+constexpr uint32_t kJoinThreads = 1024;
+constexpr uint32_t kJoinChunk = 128;
+constexpr uint32_t kJoinListLds = 6144;
+
+template <bool kTbLds>
+__global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
+  extern __shared__ uint32_t sh[];
   const uint32_t q = d.q, dl = d.delta, r = d.r;
-  const uint32_t* __restrict__ hot = d.hot;
-  if (kLds) {
-    const uint32_t words = (r << q) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh_hot[w] = d.hot[w];
-    __syncthreads();
-    hot = sh_hot;
-  }
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
   const uint64_t pairs = (uint64_t)n0 * n1;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint32_t qmask = (1u << q) - 1u, dmask = (1u << dl) - 1u;
-  uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t he0 = 0, i = 2, t = 0;
-  uint64_t x = 0;
-  bool active = p < pairs;
-  if (active) {
-    const uint32_t a = (uint32_t)(p / n1), b = (uint32_t)(p - (uint64_t)a * n1);
-    he0 = d.hse[a];
-    x = he0 ^ d.hse[(1u << q) + b];
+  if (pairs == 0) return;
+  const uint32_t* __restrict__ tb = d.hot_t;
+  const uint32_t* __restrict__ l0 = d.hse;
+  const uint32_t* __restrict__ l1 = d.hse + (1u << q);
+  uint32_t off = 0;
+  if (kTbLds) {
+    const uint32_t words = (r << q) >> 5;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
+    tb = sh;
+    off = words;
   }
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (t > dmask) {  // row i exhausted: back up one row, or take the next pair
-      if (i == 2) {
-        p += stride;
-        active = p < pairs;
-        if (active) {
-          const uint32_t a = (uint32_t)(p / n1), b = (uint32_t)(p - (uint64_t)a * n1);
-          he0 = d.hse[a];
-          x = he0 ^ d.hse[(1u << q) + b];
-          t = 0;
+  if (n0 + n1 <= kJoinListLds) {  // uniform
+    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) sh[off + j] = l0[j];
+    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) sh[off + n0 + j] = l1[j];
+    l0 = sh + off;
+    l1 = sh + off + n0;
+  }
+  __syncthreads();
+  const uint32_t lane = lane_id();
+  const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u, dmask = (1u << dl) - 1u;
+  uint64_t pool_next = 0, pool_end = 0;  // the wave's chunk (same value in every lane)
+  bool exhausted = false;
+  bool done = false, have = false;
+  uint32_t he0 = 0, top0 = 0, i = 2, R = 0;
+  uint64_t x = 0;
+  for (;;) {
+    const bool need = !done && (!have || (R == 0u && i == 2u));
+    const uint64_t need_mask = __ballot(need);
+    if (need_mask != 0) {
+      if (pool_next >= pool_end && !exhausted) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&d.ctrl->join_next, (unsigned long long)kJoinChunk);
+        base = __shfl(base, 0, kWave);
+        if (base >= pairs) {
+          exhausted = true;
+        } else {
+          pool_next = base;
+          pool_end = base + kJoinChunk < pairs ? base + kJoinChunk : pairs;
+        }
+      }
+      const uint64_t avail = pool_end - pool_next;
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(need_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
+      if (need) {
+        if (rank < avail) {
+          const uint64_t p = pool_next + rank;
+          const uint32_t a = (uint32_t)(p / n1);
+          const uint32_t b = (uint32_t)(p - (uint64_t)a * n1);
+          he0 = l0[a];
+          top0 = he0 >> (q - dl);
+          x = he0 ^ l1[b];
+          i = 2;
+          R = child_mask(tb, q, dl, 2, ((uint32_t)(x >> dl) ^ he0) & lowmask, top0) &
+              fit_mask(q, dl, 2);
+          have = true;
+        } else {
+          have = false;
+          done = exhausted;
+        }
+      }
+      const uint64_t taken = (uint64_t)__popcll(need_mask);
+      pool_next += taken < avail ? taken : avail;
+    }
+    if (__ballot(!done) == 0) break;
+    if (!have || (R == 0u && i == 2u)) continue;
+    if (R == 0u) {  // extensions of row i exhausted: back up to row i-1
+      --i;
+      const uint32_t s = (i - 2u) * dl + q;
+      const uint32_t t = (uint32_t)(x >> s) & dmask;
+      x &= (1ull << s) - 1ull;
+      R = child_mask(tb, q, dl, i, ((uint32_t)(x >> ((i - 1u) * dl)) ^ he0) & lowmask, top0) &
+          fit_mask(q, dl, i) & ~((2u << t) - 1u);
+    } else {
+      const uint32_t t = (uint32_t)__builtin_ctz(R);
+      R &= R - 1u;
+      const uint64_t xi = x | ((uint64_t)t << ((i - 2u) * dl + q));
+      if (i + 1u == r) {
+        const uint32_t addr = (uint32_t)xi;
+        if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+          const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+          if (pos < d.cand_cap) d.cand[pos] = addr;
         }
       } else {
-        --i;
-        const uint32_t sh = (i - 2) * dl + q;
-        t = (uint32_t)((x >> sh) & dmask) + 1u;
-        x &= (1ull << sh) - 1ull;
+        x = xi;
+        ++i;
+        R = child_mask(tb, q, dl, i, ((uint32_t)(x >> ((i - 1u) * dl)) ^ he0) & lowmask, top0) &
+            fit_mask(q, dl, i);
       }
-      continue;
-    }
-    const uint32_t sh = (i - 2) * dl + q;  // position of this row's new bits
-    const uint64_t xi = x | ((uint64_t)t << sh);
-    bool ok = (xi >> 32) == 0;
-    if (ok) ok = hot_bit(hot, q, i, he0 ^ ((uint32_t)(xi >> ((i - 1) * dl)) & qmask));
-    if (ok && i + 1 == r) {
-      const uint32_t addr = (uint32_t)xi;
-      if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
-        const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-        if (pos < d.cand_cap) d.cand[pos] = addr;
-      }
-      ++t;
-    } else if (ok) {
-      x = xi;
-      ++i;
-      t = 0;
-    } else {
-      ++t;
     }
   }
 }
@@ -562,10 +645,8 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
-  {
-    ProfScope ps(SPS_STAGE_SCAN_RESET, st);
-    hipLaunchKernelGGL(k_scan_reset, dim3(1), dim3(64), 0, st, d.ctrl);
-  }
+  hipError_t e = launch_scan_reset(d, true, st);
+  if (e != hipSuccess) return e;
   // SLE rows: enough blocks per row that every CU streams, at least 8 vectors per lane
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
@@ -580,11 +661,13 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
-    const uint32_t lds_bytes = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
-    if (lds_bytes <= kJoinLdsMax)
-      hipLaunchKernelGGL(k_join<true>, dim3(n_cu * 4), dim3(256), lds_bytes, st, d);
+    const uint32_t tb_bytes = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
+    const uint32_t list_bytes = kJoinListLds * 4;
+    if (tb_bytes + list_bytes <= kJoinLdsMax)
+      hipLaunchKernelGGL(k_join<true>, dim3(n_cu * 2), dim3(kJoinThreads), tb_bytes + list_bytes,
+                         st, d);
     else
-      hipLaunchKernelGGL(k_join<false>, dim3(n_cu * 4), dim3(256), 0, st, d);
+      hipLaunchKernelGGL(k_join<false>, dim3(n_cu * 2), dim3(kJoinThreads), list_bytes, st, d);
   }
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
@@ -603,10 +686,8 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const uint32_t* hosts, uint32_t n, sps_result* out,
                                  const MlpRef& mlp, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
-  {
-    ProfScope ps(SPS_STAGE_SCAN_RESET, st);
-    hipLaunchKernelGGL(k_scan_reset, dim3(1), dim3(64), 0, st, d.ctrl);
-  }
+  hipError_t e = launch_scan_reset(d, false, st);
+  if (e != hipSuccess) return e;
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
   const uint64_t want = ((uint64_t)n_cu * 8 + d.rp - 1) / d.rp;

@@ -126,17 +126,19 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ pa
   }
 }
 
-// Adam (Kingma & Ba 2015), bias-corrected, step counted from 1.
+// Adam (Kingma & Ba 2015), bias-corrected, step counted from 1.  omb1 = 1 - beta1 and
+// omb2 = 1 - beta2 come from the host in double precision (1 - 0.999f in float is off by
+// 1.3e-5 relative).
 __global__ void __launch_bounds__(256) k_mlp_adam(float* __restrict__ w, float* __restrict__ m,
                                                   float* __restrict__ v,
                                                   const float* __restrict__ grad, float lr,
-                                                  float b1, float b2, float eps, float c1,
-                                                  float c2) {
+                                                  float b1, float b2, float omb1, float omb2,
+                                                  float eps, float c1, float c2) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= (uint32_t)kP) return;
   const float g = grad[p];
-  const float mp = b1 * m[p] + (1.f - b1) * g;
-  const float vp = b2 * v[p] + (1.f - b2) * g * g;
+  const float mp = b1 * m[p] + omb1 * g;
+  const float vp = b2 * v[p] + omb2 * g * g;
   m[p] = mp;
   v[p] = vp;
   const float mh = mp / c1;
@@ -193,12 +195,13 @@ hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* ta
 }
 
 hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint32_t step,
-                           float lr, float b1, float b2, float eps, hipStream_t st) {
-  const float c1 = 1.f - powf(b1, (float)step);
-  const float c2 = 1.f - powf(b2, (float)step);
+                           float lr, double b1, double b2, float eps, hipStream_t st) {
+  const float c1 = (float)(1.0 - pow(b1, (double)step));
+  const float c2 = (float)(1.0 - pow(b2, (double)step));
+  const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2);
   ProfScope ps(SPS_STAGE_MLP, st);
   hipLaunchKernelGGL(k_mlp_adam, dim3((kP + 255) / 256), dim3(256), 0, st, w, m, v, grad, lr,
-                     b1, b2, eps, c1, c2);
+                     (float)b1, (float)b2, omb1, omb2, eps, c1, c2);
   return hipGetLastError();
 }
 

@@ -87,7 +87,7 @@ def lib():
             "sps_estimate_hosts": [vp, vp, sz, u32, vp, vp],
             "sps_mlp_work_bytes": [sz, P(sz)],
             "sps_mlp_grad": [vp, vp, vp, vp, sz, u32, vp, vp, vp, vp],
-            "sps_mlp_adam": [vp, vp, vp, vp, u32, C.c_float, C.c_float, C.c_float, C.c_float, vp],
+            "sps_mlp_adam": [vp, vp, vp, vp, u32, C.c_float, C.c_double, C.c_double, C.c_float, vp],
             "sps_mlp_forward": [vp, vp, sz, u32, C.c_int, vp, vp],
             "sps_get_tuning": [vp, P(sps_tuning)],
             "sps_set_tuning": [vp, P(sps_tuning)],

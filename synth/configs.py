@@ -56,7 +56,7 @@ def _c3_planted():
 C3_RECIPE = MultiRecipe(name="c3_distributed_merge_16", seed=0x180509246003, n_routers=16,
                         median=1 << 22, sigma=1.0, n_slices=30, window=10, n_hosts=1 << 22,
                         zipf_s=1.05, planted=_c3_planted())
-C3_PARAMS = sketch_params(q=17, r=5, delta=5, eta=8, qp=16, rp=5, etap=1024, deltap=1024,
+C3_PARAMS = sketch_params(q=17, r=10, delta=2, eta=8, qp=16, rp=5, etap=1024, deltap=1024,
                           theta=2048, seed=0x5A5A180509246003)
 C3_WINDOW, C3_THRESHOLD = 10, 2048.0
 
