@@ -73,7 +73,14 @@ typedef struct sps_pkt {
  *   theta: create-time super point threshold; fixes the sampling depth tau (Eq. 1).
  *   anet_side: 0 -> aip = dst, bip = src;  1 -> aip = src, bip = dst (Def. 1).
  *   seed: expands to the hash seeds (H1, H2, H3, RHFG[0], LH_i).
- *   cand_cap: capacity of the candidate list of one scan (0 -> 262144). */
+ *   cand_cap: capacity of the candidate list of one scan (0 -> 262144).
+ *   mode: SPS_MODE_SLIDING (u16 stamps, any window) or SPS_MODE_DISCRETE: one bit per
+ *     recorder -- the rough estimator RE (Sec. 3.2) and linear estimator LE (Sec. 4) of a
+ *     discrete time window, 16 times smaller.  A discrete sketch holds every pair since its
+ *     last sps_reset; its scans take window 1 (k = 1), its merge is a bitwise or, and
+ *     sps_features is not available.  Recorders are set with 32-bit atomic or. */
+#define SPS_MODE_SLIDING 0u
+#define SPS_MODE_DISCRETE 1u
 typedef struct sps_params {
   uint32_t q, r, delta, eta;
   uint32_t qp, rp, etap, deltap;
@@ -81,7 +88,7 @@ typedef struct sps_params {
   uint32_t anet_side;
   uint64_t seed;
   uint32_t cand_cap;
-  uint32_t reserved;
+  uint32_t mode;
 } sps_params;
 
 /* One reported host (Alg. 8 and the final filter at the end of Sec. 4). */
@@ -108,7 +115,8 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
 /* Destroy a sketch; frees library-owned memory.  Synchronizes the device first. */
 int sps_destroy(sps_sketch* s);
 
-/* Set every recorder to 0 and the current slice to 0 (stream-ordered fill kernel). */
+/* Set every recorder to 0 and the current slice to 0, and clear the scan counters
+ * (stream-ordered fill kernels). */
 int sps_reset(sps_sketch* s, void* stream);
 
 /* Per-packet update of a time slice: Alg. 3 (SRE array) and Alg. 6 (SLE array) for each of
@@ -248,8 +256,10 @@ int sps_mlp_forward(const float* d_w, const uint32_t* d_feat, size_t n, uint32_t
 int sps_state_bytes(const sps_sketch* s, size_t* bytes);
 
 /* Bit-exact state dump into host memory h_buf (checkpoint).  Layout: 64-byte header
- * (magic "SPS1", params, current slice), then u16 SRE[r][2^q][eta], then u16 SLE[r'][L'].
- * Synchronous. */
+ * (magic "SPS1", params, current slice), then the SRE array, then the SLE array.  Sliding
+ * mode: u16 SRE[r][2^q][eta], then u16 SLE[r'][L'].  Discrete mode: the SRE bits (bit
+ * ((i << q) + col) * eta + e, little-endian u32 words), then for every SLE row
+ * ceil(L' / 32) u32 words of bits (bit j = cell j).  Synchronous. */
 int sps_export(const sps_sketch* s, void* h_buf, size_t bytes, void* stream);
 
 /* Restore a dump written by sps_export of a sketch with identical parameters and seed
@@ -272,11 +282,12 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
 
 /* ---- measurement ------------------------------------------------------------------------ */
 /* Stage timing with HIP events on the stream each kernel is launched on.  While enabled
- * (process-wide), every library kernel launch is bracketed by a pair of events; reading
- * synchronizes on the recorded events and returns, per stage, the summed milliseconds and
- * the number of launches since the last read, then clears.  Not for use under stream
- * capture.  h_ms / h_launches: host arrays of nstages entries (stages beyond
- * SPS_NSTAGES are zeroed). */
+ * (process-wide), every library kernel launch of a stage whose bit is set in `stage_mask`
+ * (bit SPS_STAGE_x; 0 disables, ~0 records all) is bracketed by a pair of events, and
+ * SPS_STAGE_SCAN brackets a whole scan.  Reading synchronizes on the recorded events and
+ * returns, per stage, the summed milliseconds and the number of launches since the last
+ * read, then clears.  Launches on a capturing stream are not recorded.  h_ms / h_launches:
+ * host arrays of nstages entries (stages beyond SPS_NSTAGES are zeroed). */
 #define SPS_STAGE_INGEST 0
 #define SPS_STAGE_INGEST_BATCHED 1
 #define SPS_STAGE_MERGE 2
@@ -285,12 +296,12 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
 #define SPS_STAGE_SCAN_STATS 5
 #define SPS_STAGE_JOIN 6
 #define SPS_STAGE_ESTIMATE 7
-#define SPS_STAGE_SORT 8
+#define SPS_STAGE_SCAN 8
 #define SPS_STAGE_FEATURES 9
 #define SPS_STAGE_PROBE 10
 #define SPS_STAGE_MLP 11
 #define SPS_NSTAGES 12
-int sps_profile_enable(int on);
+int sps_profile_enable(uint32_t stage_mask);
 int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);
 
 /* Roofline probes (measurement only, not part of the method).

@@ -28,8 +28,9 @@ struct sps_sketch {
   bool owns;
   size_t bytes;
   uint16_t* state;        // == dev.sre; SRE then SLE array, contiguous
-  uint64_t state_cells;   // u16 cells of SRE + SLE arrays (incl. row padding)
-  uint64_t sre_cells;
+  uint64_t state_bytes;   // bytes of SRE + SLE arrays (incl. padding)
+  uint64_t sre_bytes;     // bytes of the SRE array (dense)
+  uint64_t row_bytes;     // bytes of one dense SLE row in a dump
   uint32_t* d_info;       // SPS_INFO_WORDS u32
   sps_result* d_sorted;   // cand_cap results (synchronous scan target)
   uint32_t* h_info;       // pinned SPS_INFO_WORDS u32
@@ -77,6 +78,7 @@ int validate(const sps_params* p) {
   if (p->qp + log2u(p->deltap) > 31) return SPS_EINVAL;  // row live counts fit u32
   if (p->theta < 1 || p->anet_side > 1) return SPS_EINVAL;
   if (effective_cand_cap(p) > (1u << 26)) return SPS_EINVAL;
+  if (p->mode > SPS_MODE_DISCRETE) return SPS_EINVAL;
   return SPS_OK;
 }
 
@@ -104,21 +106,29 @@ uint64_t splitmix64_next(uint64_t& st) {
 
 struct Layout {
   uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, total;
-  uint64_t row_len, row_stride, sre_cells, slea_cells;
+  uint64_t row_len, row_stride, sre_bytes, slea_bytes;
 };
 
 Layout layout_of(const sps_params* p) {
   Layout L{};
   const uint64_t cap = effective_cand_cap(p);
   L.row_len = ((uint64_t)1 << p->qp) * p->deltap + p->etap - p->deltap;
-  L.row_stride = round_up(L.row_len, 128);  // 256-byte rows, whole u16x8 vectors
-  L.sre_cells = ((uint64_t)p->r << p->q) * p->eta;
-  L.slea_cells = (uint64_t)p->rp * L.row_stride;
+  const uint64_t sre_cells = ((uint64_t)p->r << p->q) * p->eta;
+  if (p->mode == SPS_MODE_DISCRETE) {
+    // bits; a row ends with at least one spare word so 32-bit windows never cross it
+    L.row_stride = round_up(L.row_len + 32, 1024);
+    L.sre_bytes = sre_cells / 8;
+    L.slea_bytes = (uint64_t)p->rp * L.row_stride / 8;
+  } else {
+    L.row_stride = round_up(L.row_len, 128);  // 256-byte rows, whole u16x8 vectors
+    L.sre_bytes = sre_cells * 2;
+    L.slea_bytes = (uint64_t)p->rp * L.row_stride * 2;
+  }
   uint64_t o = 0;
   L.ctrl = o;   o += sizeof(Ctrl);
   L.info = o;   o += 256;
-  L.sre = o;    o += round_up(L.sre_cells * 2, 256);
-  L.slea = o;   o += round_up(L.slea_cells * 2, 256);
+  L.sre = o;    o += round_up(L.sre_bytes, 256);
+  L.slea = o;   o += round_up(L.slea_bytes, 256);
   L.hot = o;    o += round_up(((uint64_t)p->r << p->q) / 8, 256);
   L.hot_t = o;  o += round_up(((uint64_t)p->r << p->q) / 8, 256);
   L.hse = o;    o += round_up(((uint64_t)2 << p->q) * 4, 256);
@@ -132,7 +142,7 @@ Layout layout_of(const sps_params* p) {
 bool same_shape(const sps_params& a, const sps_params& b) {
   return a.q == b.q && a.r == b.r && a.delta == b.delta && a.eta == b.eta && a.qp == b.qp &&
          a.rp == b.rp && a.etap == b.etap && a.deltap == b.deltap && a.theta == b.theta &&
-         a.anet_side == b.anet_side && a.seed == b.seed;
+         a.anet_side == b.anet_side && a.seed == b.seed && a.mode == b.mode;
 }
 
 int check_slice(const sps_sketch* s, uint32_t slice) {
@@ -148,7 +158,7 @@ struct Header {  // 64-byte dump header
 static_assert(sizeof(Header) == 64, "dump header is 64 bytes");
 
 // ---- stage timing ----------------------------------------------------------------------
-std::atomic<bool> g_prof_on{false};
+std::atomic<uint32_t> g_prof_mask{0};
 std::mutex g_prof_mu;
 struct ProfRec {
   int stage;
@@ -179,7 +189,7 @@ int device_cu_count() {
 
 namespace sps {
 ProfScope::ProfScope(int stage, hipStream_t st) : stage_(stage), st_(st), ev0_(nullptr) {
-  if (!g_prof_on.load(std::memory_order_relaxed)) return;
+  if (!((g_prof_mask.load(std::memory_order_relaxed) >> stage) & 1u)) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> g(g_prof_mu);
@@ -199,8 +209,8 @@ ProfScope::~ProfScope() {
 
 extern "C" {
 
-int sps_profile_enable(int on) {
-  g_prof_on.store(on != 0);
+int sps_profile_enable(uint32_t stage_mask) {
+  g_prof_mask.store(stage_mask);
   return SPS_OK;
 }
 
@@ -323,6 +333,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.hot_cut = hot_cut_of(p->eta);
   d.anet_side = p->anet_side;
   d.cand_cap = s->p.cand_cap;
+  d.mode = p->mode;
   uint64_t st = p->seed;
   d.seed_h1 = (uint32_t)splitmix64_next(st);
   d.seed_h2 = (uint32_t)splitmix64_next(st);
@@ -330,8 +341,9 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.seed_rhfg0 = (uint32_t)splitmix64_next(st);
   for (int i = 0; i < sps::kMaxRP; ++i) d.seed_lh[i] = (uint32_t)splitmix64_next(st);
   s->state = d.sre;
-  s->sre_cells = L.sre_cells;
-  s->state_cells = (L.slea - L.sre) / 2 + L.slea_cells;
+  s->sre_bytes = L.sre_bytes;
+  s->state_bytes = (L.slea - L.sre) + L.slea_bytes;
+  s->row_bytes = p->mode == SPS_MODE_DISCRETE ? (L.row_len + 31) / 32 * 4 : L.row_len * 2;
   s->cur = 0;
   s->mlp.w = nullptr;
   s->tune.blocks_per_cu = 16;
@@ -354,7 +366,8 @@ int sps_destroy(sps_sketch* s) {
 
 int sps_reset(sps_sketch* s, void* stream) {
   if (!s) return SPS_EINVAL;
-  SPS_HIP(sps::launch_fill_zero(s->state, s->state_cells * 2, (hipStream_t)stream));
+  SPS_HIP(sps::launch_fill_zero(s->state, s->state_bytes, (hipStream_t)stream));
+  SPS_HIP(sps::launch_scan_reset(s->dev, true, (hipStream_t)stream));
   s->cur = 0;
   return SPS_OK;
 }
@@ -551,7 +564,9 @@ int sps_merge(sps_sketch* dst, const sps_sketch* const* h_src, uint32_t nsrc, vo
     srcs[j] = h_src[j]->state;
     if (h_src[j]->cur > cur) cur = h_src[j]->cur;
   }
-  if (nsrc) SPS_HIP(sps::launch_merge(dst->state, srcs, nsrc, dst->state_cells, (hipStream_t)stream));
+  if (nsrc)
+    SPS_HIP(sps::launch_merge(dst->state, srcs, nsrc, dst->state_bytes,
+                              dst->p.mode == SPS_MODE_DISCRETE, (hipStream_t)stream));
   dst->cur = cur;
   return SPS_OK;
 }
@@ -560,6 +575,7 @@ int sps_scan_async(sps_sketch* s, uint32_t window, double threshold, sps_result*
                    size_t cap, uint32_t* d_info, void* stream) {
   if (!s || !d_info || (cap && !d_out)) return SPS_EINVAL;
   if (window < 1 || window > 65534u) return SPS_EINVAL;
+  if (s->p.mode == SPS_MODE_DISCRETE && window != 1) return SPS_EINVAL;
   if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
   SPS_HIP(sps::launch_scan(s->dev, s->cur, window, threshold, d_out, (uint32_t)cap, d_info,
                            s->mlp, s->n_cu, (hipStream_t)stream));
@@ -592,7 +608,7 @@ int sps_scan(sps_sketch* s, uint32_t window, double threshold, sps_result* h_out
 int sps_features(const sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_t window,
                  uint32_t* d_x, void* stream) {
   if (!s || (n && (!d_hosts || !d_x))) return SPS_EINVAL;
-  if (window < 1 || window > 32) return SPS_EINVAL;
+  if (window < 1 || window > 32 || s->p.mode == SPS_MODE_DISCRETE) return SPS_EINVAL;
   SPS_HIP(sps::launch_features(s->dev, s->cur, window, d_hosts, n, d_x, s->n_cu,
                                (hipStream_t)stream));
   return SPS_OK;
@@ -602,6 +618,7 @@ int sps_estimate_hosts(sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_
                        sps_result* d_out, void* stream) {
   if (!s || (n && (!d_hosts || !d_out))) return SPS_EINVAL;
   if (window < 1 || window > 65534u || n > 0xFFFFFFFFull) return SPS_EINVAL;
+  if (s->p.mode == SPS_MODE_DISCRETE && window != 1) return SPS_EINVAL;
   SPS_HIP(sps::launch_estimate_hosts(s->dev, s->cur, window, d_hosts, (uint32_t)n, d_out, s->mlp,
                                      s->n_cu, (hipStream_t)stream));
   return SPS_OK;
@@ -665,7 +682,7 @@ int sps_mlp_forward(const float* d_w, const uint32_t* d_feat, size_t n, uint32_t
 int sps_state_bytes(const sps_sketch* s, size_t* bytes) {
   if (!s || !bytes) return SPS_EINVAL;
   const Dev& d = s->dev;
-  *bytes = sizeof(Header) + (size_t)s->sre_cells * 2 + (size_t)d.rp * d.row_len * 2;
+  *bytes = sizeof(Header) + (size_t)s->sre_bytes + (size_t)d.rp * s->row_bytes;
   return SPS_OK;
 }
 
@@ -684,10 +701,12 @@ int sps_export(const sps_sketch* s, void* h_buf, size_t bytes, void* stream) {
   uint8_t* o = static_cast<uint8_t*>(h_buf) + sizeof(Header);
   const Dev& d = s->dev;
   SPS_HIP(hipStreamSynchronize(st));
-  SPS_HIP(hipMemcpy(o, d.sre, (size_t)s->sre_cells * 2, hipMemcpyDeviceToHost));
-  o += (size_t)s->sre_cells * 2;
-  SPS_HIP(hipMemcpy2D(o, (size_t)d.row_len * 2, d.slea, (size_t)d.row_stride * 2,
-                      (size_t)d.row_len * 2, d.rp, hipMemcpyDeviceToHost));
+  const size_t pitch = d.mode == SPS_MODE_DISCRETE ? (size_t)d.row_stride / 8
+                                                   : (size_t)d.row_stride * 2;
+  SPS_HIP(hipMemcpy(o, d.sre, (size_t)s->sre_bytes, hipMemcpyDeviceToHost));
+  o += (size_t)s->sre_bytes;
+  SPS_HIP(hipMemcpy2D(o, (size_t)s->row_bytes, d.slea, pitch, (size_t)s->row_bytes, d.rp,
+                      hipMemcpyDeviceToHost));
   return SPS_OK;
 }
 
@@ -702,16 +721,17 @@ int sps_import(sps_sketch* s, const void* h_buf, size_t bytes, void* stream) {
   sps_params want = s->p;
   if (memcmp(h.magic, "SPS1", 4) != 0) return SPS_EINVAL;
   h.p.cand_cap = want.cand_cap;
-  h.p.reserved = want.reserved;
   if (!same_shape(h.p, want) || h.cur > 65534u) return SPS_EMISMATCH;
   hipStream_t st = (hipStream_t)stream;
   const Dev& d = s->dev;
   const uint8_t* o = static_cast<const uint8_t*>(h_buf) + sizeof(Header);
   SPS_HIP(hipStreamSynchronize(st));
-  SPS_HIP(hipMemcpy(d.sre, o, (size_t)s->sre_cells * 2, hipMemcpyHostToDevice));
-  o += (size_t)s->sre_cells * 2;
-  SPS_HIP(hipMemcpy2D(d.slea, (size_t)d.row_stride * 2, o, (size_t)d.row_len * 2,
-                      (size_t)d.row_len * 2, d.rp, hipMemcpyHostToDevice));
+  const size_t pitch = d.mode == SPS_MODE_DISCRETE ? (size_t)d.row_stride / 8
+                                                   : (size_t)d.row_stride * 2;
+  SPS_HIP(hipMemcpy(d.sre, o, (size_t)s->sre_bytes, hipMemcpyHostToDevice));
+  o += (size_t)s->sre_bytes;
+  SPS_HIP(hipMemcpy2D(d.slea, pitch, o, (size_t)s->row_bytes, (size_t)s->row_bytes, d.rp,
+                      hipMemcpyHostToDevice));
   s->cur = h.cur;
   return SPS_OK;
 }
@@ -742,13 +762,13 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
       Ctrl c;
       SPS_HIP(hipStreamSynchronize((hipStream_t)stream));
       SPS_HIP(hipMemcpy(&c, d.ctrl, sizeof(c), hipMemcpyDeviceToHost));
-      const uint32_t n = c.n_cand < d.cand_cap ? c.n_cand : d.cand_cap;
+      const uint32_t n = c.last_n_cand < d.cand_cap ? c.last_n_cand : d.cand_cap;
       src = d.cand;
       full = (size_t)n * 4;
       break;
     }
     case 2:
-      src = reinterpret_cast<const uint8_t*>(d.ctrl) + offsetof(Ctrl, row_live);
+      src = reinterpret_cast<const uint8_t*>(d.ctrl) + offsetof(Ctrl, last_row_live);
       full = (size_t)d.rp * 4;
       break;
     default: return SPS_EINVAL;

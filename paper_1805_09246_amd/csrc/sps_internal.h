@@ -13,15 +13,24 @@ constexpr int kMaxR = 32;      // SRE-array rows supported
 constexpr int kMaxBatch = 64;  // routers per batched launch
 constexpr int kMaxMerge = 32;  // sources per merge launch (more are chained)
 
-// Per-scan counters kept in device memory (one 256-byte block per sketch).
+// Per-scan counters kept in device memory (one 256-byte block per sketch).  Every scan
+// leaves the working fields zero when it ends (its last kernel clears them), so a scan
+// needs no reset launch and replays of a captured scan start clean.
 struct Ctrl {
   uint32_t row_live[kMaxRP];  // live cells of every SLE-array row (Def. 4 numerators)
   uint32_t hse_count[2];      // hot SREs found in rows 0 and 1
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
   uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
   unsigned long long join_next;  // next (he0, he1) pair handed out by the join
-  uint32_t pad[64 - kMaxRP - 4 - 2];
+  uint32_t blocks_done;       // estimate blocks finished (the last one orders the results)
+  uint32_t pad0;
+  // copies of the last scan's counters, for inspection (not cleared)
+  uint32_t last_row_live[kMaxRP];
+  uint32_t last_n_cand;
+  uint32_t last_hse[2];
+  uint32_t pad[64 - 2 * kMaxRP - 4 - 2 - 2 - 3];
 };
+constexpr uint32_t kCtrlWorkingWords = kMaxRP + 4 + 2 + 2;  // fields cleared after a scan
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte block");
 
 // Learned-estimator attachment (weights in device memory, bounds by value).
@@ -35,8 +44,8 @@ struct MlpRef {
 
 // Everything a kernel needs to know about one sketch; passed by value.
 struct Dev {
-  uint16_t* sre;          // [r][2^q][eta]
-  uint16_t* slea;         // [r'][row_stride], cells >= row_len are padding (always 0)
+  uint16_t* sre;          // [r][2^q][eta] stamps (discrete mode: bits, as u32 words)
+  uint16_t* slea;         // [r'][row_stride] cells >= row_len are padding (always 0)
   uint32_t* hot;          // [r][2^q / 32] hot-SRE bitmap
   uint32_t* hot_t;        // [r][2^q / 32] the same bits transposed for the join: bit
                           // (low << delta) + top of row i is hot_i[low | top << (q - delta)]
@@ -52,6 +61,7 @@ struct Dev {
   uint32_t hot_cut;
   uint32_t anet_side;
   uint32_t cand_cap;
+  uint32_t mode;          // SPS_MODE_SLIDING: u16 stamps; SPS_MODE_DISCRETE: one bit per cell
   uint32_t seed_h1, seed_h2, seed_h3, seed_rhfg0;
   uint32_t seed_lh[kMaxRP];
 };
@@ -104,8 +114,9 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
                                  uint32_t tile, uint16_t stamp, int blocks, int threads,
                                  hipStream_t st);
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
+hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st);
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
-                        uint64_t cells, hipStream_t st);
+                        uint64_t bytes, bool bits, hipStream_t st);
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st);

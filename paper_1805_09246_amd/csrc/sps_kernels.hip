@@ -37,11 +37,18 @@ __device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__
   const uint32_t bip = d.anet_side ? dst : src;
   const uint32_t z = fmix32(bip ^ d.seed_h3) & (d.etap - 1u);
   const uint32_t qpmask = (1u << d.qp) - 1u;
+  const bool bits = d.mode == SPS_MODE_DISCRETE;  // uniform
+  uint32_t* const slea_w = reinterpret_cast<uint32_t*>(slea);
+  uint32_t* const sre_w = reinterpret_cast<uint32_t*>(sre);
 #pragma unroll
   for (int i = 0; i < kMaxRP; ++i) {
     if (i < (int)d.rp) {
       const uint32_t j = fmix32(aip ^ d.seed_lh[i]) & qpmask;
-      slea[(uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z] = stamp;
+      const uint64_t cell = (uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z;
+      if (bits)
+        atomicOr(&slea_w[cell >> 5], 1u << (cell & 31u));
+      else
+        slea[cell] = stamp;
     }
   }
   const uint32_t h1 = fmix32(bip ^ d.seed_h1);
@@ -49,10 +56,13 @@ __device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__
     const uint32_t e = fmix32(bip ^ d.seed_h2) & (d.eta - 1u);
     const uint32_t qmask = (1u << d.q) - 1u;
     const uint32_t c0 = fmix32(aip ^ d.seed_rhfg0) & qmask;
-    sre[((uint64_t)c0 << __builtin_ctz(d.eta)) + e] = stamp;
-    for (uint32_t i = 1; i < d.r; ++i) {
-      const uint32_t col = ((aip >> ((i - 1u) * d.delta)) ^ c0) & qmask;
-      sre[((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e] = stamp;
+    for (uint32_t i = 0; i < d.r; ++i) {
+      const uint32_t col = i == 0 ? c0 : ((aip >> ((i - 1u) * d.delta)) ^ c0) & qmask;
+      const uint64_t cell = ((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e;
+      if (bits)
+        atomicOr(&sre_w[cell >> 5], 1u << (cell & 31u));
+      else
+        sre[cell] = stamp;
     }
   }
 }
@@ -146,18 +156,22 @@ struct MergeSrcs {
 };
 
 __global__ void __launch_bounds__(256) k_merge_max(u16x8* __restrict__ dst, MergeSrcs s,
-                                                   uint32_t nsrc, uint64_t nvec) {
+                                                   uint32_t nsrc, uint64_t nvec, int bits) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
     u16x8 v = dst[i];
-    for (uint32_t j = 0; j < nsrc; ++j) v = __builtin_elementwise_max(v, s.p[j][i]);
+    if (bits) {  // discrete mode: the union of recorder bits
+      for (uint32_t j = 0; j < nsrc; ++j) v = v | s.p[j][i];
+    } else {
+      for (uint32_t j = 0; j < nsrc; ++j) v = __builtin_elementwise_max(v, s.p[j][i]);
+    }
     dst[i] = v;
   }
 }
 
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
-                        uint64_t cells, hipStream_t st) {
-  const uint64_t nvec = cells / 8;
+                        uint64_t bytes, bool bits, hipStream_t st) {
+  const uint64_t nvec = bytes / 16;
   uint64_t blocks = (nvec + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   for (uint32_t b = 0; b < nsrc; b += kMaxMerge) {
@@ -166,7 +180,7 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
     for (uint32_t j = 0; j < k; ++j) s.p[j] = reinterpret_cast<const u16x8*>(srcs[b + j]);
     ProfScope ps(SPS_STAGE_MERGE, st);
     hipLaunchKernelGGL(k_merge_max, dim3((uint32_t)blocks), dim3(256), 0, st,
-                       reinterpret_cast<u16x8*>(dst), s, k, nvec);
+                       reinterpret_cast<u16x8*>(dst), s, k, nvec, bits ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -179,7 +193,7 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
 __global__ void __launch_bounds__(256) k_scan_reset(Ctrl* c, uint32_t* hot_t, uint32_t words) {
   if (blockIdx.x == 0) {
     uint32_t* w = reinterpret_cast<uint32_t*>(c);
-    for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kCtrlWorkingWords; i += blockDim.x) w[i] = 0;
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
     hot_t[i] = 0;
@@ -224,14 +238,24 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
     const uint64_t step = (uint64_t)nb_row * blockDim.x;
     uint32_t cnt = 0;
     uint64_t v = (uint64_t)chunk * blockDim.x + threadIdx.x;
-    for (; v + 3 * step < nvec; v += 4 * step) {  // four independent loads in flight
-      const u32x4 a = __builtin_nontemporal_load(&rowp[v]);
-      const u32x4 b = __builtin_nontemporal_load(&rowp[v + step]);
-      const u32x4 c = __builtin_nontemporal_load(&rowp[v + 2 * step]);
-      const u32x4 e = __builtin_nontemporal_load(&rowp[v + 3 * step]);
-      cnt += live8(a, lo) + live8(b, lo) + live8(c, lo) + live8(e, lo);
+    if (d.mode == SPS_MODE_DISCRETE) {  // bits: a row is row_stride / 128 vectors
+      const u32x4* rowb = reinterpret_cast<const u32x4*>(
+          reinterpret_cast<const uint32_t*>(d.slea) + (uint64_t)row * (d.row_stride >> 5));
+      const uint64_t nvb = d.row_stride >> 7;
+      for (; v < nvb; v += step) {
+        const u32x4 a = __builtin_nontemporal_load(&rowb[v]);
+        cnt += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+      }
+    } else {
+      for (; v + 3 * step < nvec; v += 4 * step) {  // four independent loads in flight
+        const u32x4 a = __builtin_nontemporal_load(&rowp[v]);
+        const u32x4 b = __builtin_nontemporal_load(&rowp[v + step]);
+        const u32x4 c = __builtin_nontemporal_load(&rowp[v + 2 * step]);
+        const u32x4 e = __builtin_nontemporal_load(&rowp[v + 3 * step]);
+        cnt += live8(a, lo) + live8(b, lo) + live8(c, lo) + live8(e, lo);
+      }
+      for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
     }
-    for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
     cnt = wave_sum(cnt);
     if (lane_id() == 0) red[threadIdx.x / kWave] = cnt;
     __syncthreads();
@@ -245,9 +269,14 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
   const uint64_t sre_idx = (uint64_t)(b - slea_blocks) * blockDim.x + threadIdx.x;
   const uint64_t n_sre = (uint64_t)d.r << d.q;  // multiple of 64 (q >= 6)
   if (sre_idx - lane_id() >= n_sre) return;     // whole wave out of range
-  const u32x4* cell = reinterpret_cast<const u32x4*>(d.sre + (sre_idx << __builtin_ctz(d.eta)));
   uint32_t w = 0;
-  for (uint32_t v = 0; v < d.eta / 8; ++v) w += live8(cell[v], lo);
+  if (d.mode == SPS_MODE_DISCRETE) {  // eta bits per SRE: eta / 8 bytes
+    const uint8_t* by = reinterpret_cast<const uint8_t*>(d.sre) + (sre_idx * d.eta >> 3);
+    for (uint32_t b = 0; b < d.eta / 8; ++b) w += __popc((uint32_t)by[b]);
+  } else {
+    const u32x4* cell = reinterpret_cast<const u32x4*>(d.sre + (sre_idx << __builtin_ctz(d.eta)));
+    for (uint32_t v = 0; v < d.eta / 8; ++v) w += live8(cell[v], lo);
+  }
   const bool hot = w >= d.hot_cut;
   const uint64_t mask = __ballot(hot);
   const uint32_t row = (uint32_t)(sre_idx >> d.q);
@@ -443,7 +472,27 @@ __device__ __forceinline__ void usle_counts(const Dev& d, uint32_t x, uint32_t c
   uint32_t c_live = 0, c_age[32];
   for (uint32_t a = 0; a < 32; ++a) c_age[a] = 0;
   const bool vec = ((d.deltap & 7u) == 0) && ((d.etap & 7u) == 0);  // uniform
-  if (vec) {
+  if (d.mode == SPS_MODE_DISCRETE) {
+    // bits: lane takes 32 consecutive cells per pass; a cell of the union is set only when
+    // set in every row (the window of 32 bits may straddle two words)
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(d.slea);
+    for (uint32_t z0 = 0; z0 < d.etap; z0 += 32 * kWave) {
+      const uint32_t z = z0 + lane * 32;
+      if (z < d.etap) {
+        uint32_t m = d.etap - z >= 32u ? 0xFFFFFFFFu : ((1u << (d.etap - z)) - 1u);
+#pragma unroll
+        for (int i = 0; i < kMaxRP; ++i)
+          if (i < (int)d.rp) {
+            const uint64_t b = base[i] + z;
+            const uint32_t sh = (uint32_t)(b & 31u);
+            const uint32_t w0 = w[b >> 5];
+            const uint32_t v = sh ? (w0 >> sh) | (w[(b >> 5) + 1] << (32u - sh)) : w0;
+            m &= v;
+          }
+        c_live += __popc(m);
+      }
+    }
+  } else if (vec) {
     for (uint32_t z0 = 0; z0 < d.etap; z0 += 8 * kWave) {
       const uint32_t z = z0 + lane * 8;
       if (z < d.etap) {
@@ -535,15 +584,75 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
+// Stage 4 (run by the last estimate block): order the kept hosts ascending.  Hosts are
+// distinct, so a host's rank is the number of smaller kept hosts; the block counts over LDS
+// tiles of the list.  Then the info words, the inspection copies, and the working counters
+// cleared for the next scan.
+constexpr int kSortTile = 4096;
+
+__device__ void order_and_finish(const Dev& d, sps_result* __restrict__ out, uint32_t cap,
+                                 uint32_t* __restrict__ info, uint32_t* tile) {
+  Ctrl* c = d.ctrl;
+  const uint32_t n = min(c->n_kept, d.cand_cap);
+  if (out) {
+    for (uint32_t base = 0; base < n; base += blockDim.x) {
+      const uint32_t i = base + threadIdx.x;
+      const uint32_t h = i < n ? d.kept[i].host : 0u;
+      uint32_t rank = 0;
+      for (uint32_t t0 = 0; t0 < n; t0 += kSortTile) {
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile && t0 + j < n; j += blockDim.x)
+          tile[j] = d.kept[t0 + j].host;
+        __syncthreads();
+        const uint32_t m = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
+#pragma unroll 8
+        for (uint32_t j = 0; j < m; ++j) rank += tile[j] < h;
+      }
+      if (i < n && rank < cap) out[rank] = d.kept[i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (info) {
+      info[SPS_INFO_KEPT] = c->n_kept;
+      info[SPS_INFO_CAND] = c->n_cand;
+      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
+      info[SPS_INFO_HSE0] = c->hse_count[0];
+      info[SPS_INFO_HSE1] = c->hse_count[1];
+      info[5] = 0;
+      info[6] = 0;
+      info[7] = 0;
+    }
+    for (uint32_t i = 0; i < (uint32_t)kMaxRP; ++i) c->last_row_live[i] = c->row_live[i];
+    c->last_n_cand = c->n_cand;
+    c->last_hse[0] = c->hse_count[0];
+    c->last_hse[1] = c->hse_count[1];
+  }
+  __syncthreads();
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < kCtrlWorkingWords; i += blockDim.x) w[i] = 0;
+}
+
 // Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.  With a host
 // list (`hosts` non-null) every host is estimated and written to direct[c] unfiltered.
+// In a scan the blocks first clear the join's table (the join has finished), and the block
+// that finishes last orders the kept hosts into `out` and clears the counters.
 __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t lo, uint32_t k,
                                                   double threshold, MlpRef mlp,
                                                   const uint32_t* __restrict__ hosts,
                                                   uint32_t n_hosts,
-                                                  sps_result* __restrict__ direct) {
+                                                  sps_result* __restrict__ direct,
+                                                  sps_result* __restrict__ out, uint32_t cap,
+                                                  uint32_t* __restrict__ info) {
+  __shared__ uint32_t tile[kSortTile];
+  __shared__ uint32_t last;
   const uint32_t n = hosts ? n_hosts : min(d.ctrl->n_cand, d.cand_cap);
   const uint32_t* __restrict__ src = hosts ? hosts : d.cand;
+  if (!hosts) {
+    const uint32_t words = (d.r << d.q) >> 5;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x)
+      d.hot_t[w] = 0;
+  }
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t lane = lane_id();
   const bool use_mlp = mlp.w != nullptr && k == SPS_MLP_IN;
@@ -601,43 +710,16 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       }
     }
   }
-}
-
-// Stage 4: order the kept hosts ascending.  Hosts are distinct, so a host's rank is the
-// number of smaller kept hosts; every lane counts for one host over LDS tiles of the list.
-constexpr int kSortThreads = 1024;
-constexpr int kSortTile = 4096;
-
-__global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
-                                                            uint32_t cap,
-                                                            uint32_t* __restrict__ info) {
-  __shared__ uint32_t tile[kSortTile];
-  const uint32_t n = min(d.ctrl->n_kept, d.cand_cap);
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t h = i < n ? d.kept[i].host : 0u;
-    uint32_t rank = 0;
-    for (uint32_t t0 = 0; t0 < n; t0 += kSortTile) {
-      __syncthreads();
-      for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile && t0 + j < n; j += blockDim.x)
-        tile[j] = d.kept[t0 + j].host;
-      __syncthreads();
-      const uint32_t m = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
-#pragma unroll 8
-      for (uint32_t j = 0; j < m; ++j) rank += tile[j] < h;
-    }
-    if (i < n && rank < cap) out[rank] = d.kept[i];
+  // the last block to finish sees every block's results
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&d.ctrl->blocks_done, 1u) == gridDim.x - 1u;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && info) {
-    const Ctrl* c = d.ctrl;
-    info[SPS_INFO_KEPT] = c->n_kept;
-    info[SPS_INFO_CAND] = c->n_cand;
-    info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
-    info[SPS_INFO_HSE0] = c->hse_count[0];
-    info[SPS_INFO_HSE1] = c->hse_count[1];
-    info[5] = 0;
-    info[6] = 0;
-    info[7] = 0;
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    order_and_finish(d, out, cap, info, tile);
   }
 }
 
@@ -645,8 +727,7 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
-  hipError_t e = launch_scan_reset(d, true, st);
-  if (e != hipSuccess) return e;
+  ProfScope whole(SPS_STAGE_SCAN, st);
   // SLE rows: enough blocks per row that every CU streams, at least 8 vectors per lane
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
@@ -672,22 +753,18 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
     hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
-                       threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr);
-  }
-  {
-    ProfScope ps(SPS_STAGE_SORT, st);
-    hipLaunchKernelGGL(k_rank_sort, dim3(32), dim3(kSortThreads), 0, st, d, out, cap, info);
+                       threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr, out,
+                       cap, info);
   }
   return hipGetLastError();
 }
 
-// Estimates of given hosts: SLE row live counts, then the estimate of every host.
+// Estimates of given hosts: SLE row live counts, then the estimate of every host (its last
+// block clears the counters).
 hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const uint32_t* hosts, uint32_t n, sps_result* out,
                                  const MlpRef& mlp, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
-  hipError_t e = launch_scan_reset(d, false, st);
-  if (e != hipSuccess) return e;
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
   const uint64_t want = ((uint64_t)n_cu * 8 + d.rp - 1) / d.rp;
@@ -699,13 +776,12 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
     hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row)), dim3(256), 0, st, d, lo,
                        (uint32_t)nb_row);
   }
-  if (n) {
-    uint32_t blocks = (n + 3) / 4;
-    if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
-    ProfScope ps(SPS_STAGE_ESTIMATE, st);
-    hipLaunchKernelGGL(k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
-                       hosts, n, out);
-  }
+  if (n == 0) return launch_scan_reset(d, false, st);  // only the counters to clear
+  uint32_t blocks = (n + 3) / 4;
+  if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
+  ProfScope ps(SPS_STAGE_ESTIMATE, st);
+  hipLaunchKernelGGL(k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
+                     hosts, n, out, (sps_result*)nullptr, 0u, (uint32_t*)nullptr);
   return hipGetLastError();
 }
 

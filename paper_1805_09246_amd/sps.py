@@ -35,7 +35,7 @@ EXPORTS = [
     "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
-          "estimate", "sort", "features", "probe", "mlp"]
+          "estimate", "scan", "features", "probe", "mlp"]
 
 
 class sps_tuning(C.Structure):
@@ -52,7 +52,7 @@ class sps_params(C.Structure):
     _fields_ = [("q", C.c_uint32), ("r", C.c_uint32), ("delta", C.c_uint32), ("eta", C.c_uint32),
                 ("qp", C.c_uint32), ("rp", C.c_uint32), ("etap", C.c_uint32),
                 ("deltap", C.c_uint32), ("theta", C.c_uint32), ("anet_side", C.c_uint32),
-                ("seed", C.c_uint64), ("cand_cap", C.c_uint32), ("reserved", C.c_uint32)]
+                ("seed", C.c_uint64), ("cand_cap", C.c_uint32), ("mode", C.c_uint32)]
 
 
 RESULT_DTYPE = np.dtype([("host", "<u4"), ("live", "<u4"), ("flags", "<u4"), ("pad", "<u4"),
@@ -103,7 +103,7 @@ def lib():
             "sps_derived": [vp, P(u32), P(u32), P(u64)],
             "sps_debug_copy": [vp, i32, vp, sz, P(sz), vp],
             "sps_sync": [vp],
-            "sps_profile_enable": [i32],
+            "sps_profile_enable": [u32],
             "sps_profile_read": [vp, vp, i32],
             "sps_probe_scatter": [vp, u64, u64, u32, C.c_uint16, vp],
             "sps_probe_stream": [vp, u64, vp, vp],
@@ -328,8 +328,17 @@ def sps_strerror(code: int) -> str:
     return strerror(code)
 
 
-def sps_profile_enable(on: bool):
-    _check(lib().sps_profile_enable(1 if on else 0), "sps_profile_enable")
+def sps_profile_enable(on, stages=None):
+    """on: False disables; True records every stage, or only the named `stages`."""
+    if not on:
+        mask = 0
+    elif stages is None:
+        mask = 0xFFFFFFFF
+    else:
+        mask = 0
+        for st in stages:
+            mask |= 1 << STAGES.index(st)
+    _check(lib().sps_profile_enable(mask), "sps_profile_enable")
 
 
 def sps_profile_read() -> dict:
@@ -457,10 +466,23 @@ class Sketch:
         return split_dump(self.export(stream), self.params)
 
 
+MODE_SLIDING, MODE_DISCRETE = 0, 1
+
+
 def split_dump(buf: np.ndarray, params: dict):
+    """Sliding mode: (u16 SRE (r, 2^q, eta), u16 SLE array (r', L')).  Discrete mode: the
+    same shapes as uint8 0/1 arrays of the recorder bits."""
     p = params
     n_sre = (p["r"] << p["q"]) * p["eta"]
     row_len = (1 << p["qp"]) * p["deltap"] + p["etap"] - p["deltap"]
+    if p.get("mode", 0) == MODE_DISCRETE:
+        body = buf[HEADER_BYTES:]
+        sre = np.unpackbits(body[:n_sre // 8], bitorder="little").reshape(
+            p["r"], 1 << p["q"], p["eta"])
+        rw = (row_len + 31) // 32 * 4
+        rows = body[n_sre // 8:n_sre // 8 + p["rp"] * rw].reshape(p["rp"], rw)
+        slea = np.unpackbits(rows, axis=1, bitorder="little")[:, :row_len]
+        return sre, slea
     body = buf[HEADER_BYTES:].view(np.uint16)
     sre = body[:n_sre].reshape(p["r"], 1 << p["q"], p["eta"])
     slea = body[n_sre:n_sre + p["rp"] * row_len].reshape(p["rp"], row_len)
