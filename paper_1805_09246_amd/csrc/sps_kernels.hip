@@ -725,31 +725,44 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
 
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       int n_cu, hipStream_t st) {
+                       int n_cu, hipStream_t st, const ScanStreams& ss) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // SLE rows: enough blocks per row that every CU streams, at least 8 vectors per lane
+  // The SLE-array stream (row live counts, HBM bound) only feeds the estimate, and the hot
+  // SREs + join (LDS / ALU bound) do not read it: the stream runs on the auxiliary stream
+  // beside them, with about half of each CU's wave slots, and is joined before the estimate.
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
-  const uint64_t want = ((uint64_t)n_cu * 8 + d.rp - 1) / d.rp;
+  const uint64_t want = ((uint64_t)n_cu * 4 + d.rp - 1) / d.rp;
   if (nb_row > want) nb_row = want;
   if (nb_row < 1) nb_row = 1;
+  hipError_t e = hipEventRecord(ss.fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ss.aux, ss.fork, 0);
+  if (e != hipSuccess) return e;
+  {
+    ProfScope ps(SPS_STAGE_SCAN_STATS, ss.aux);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row)), dim3(256), 0, ss.aux, d,
+                       lo, (uint32_t)nb_row);
+  }
+  e = hipEventRecord(ss.join, ss.aux);
+  if (e != hipSuccess) return e;
   const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
   {
-    ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row + sre_blocks)), dim3(256),
-                       0, st, d, lo, (uint32_t)nb_row);
+    ProfScope ps(SPS_STAGE_SCAN_HOT, st);  // the hot-SRE part: nb_row = 0, SRE blocks only
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)sre_blocks), dim3(256), 0, st, d, lo, 0u);
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
     const uint32_t tb_bytes = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
     const uint32_t list_bytes = kJoinListLds * 4;
     if (tb_bytes + list_bytes <= kJoinLdsMax)
-      hipLaunchKernelGGL(k_join<true>, dim3(n_cu * 2), dim3(kJoinThreads), tb_bytes + list_bytes,
+      hipLaunchKernelGGL(k_join<true>, dim3(n_cu), dim3(kJoinThreads), tb_bytes + list_bytes,
                          st, d);
     else
-      hipLaunchKernelGGL(k_join<false>, dim3(n_cu * 2), dim3(kJoinThreads), list_bytes, st, d);
+      hipLaunchKernelGGL(k_join<false>, dim3(n_cu), dim3(kJoinThreads), list_bytes, st, d);
   }
+  e = hipStreamWaitEvent(st, ss.join, 0);
+  if (e != hipSuccess) return e;
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
     hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
