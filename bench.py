@@ -119,13 +119,14 @@ def merge_extra(log_fn):
     cap = 8192
     res = torch.zeros((n_sl, cap * 24), dtype=torch.uint8, device="cuda")
     info = torch.zeros((n_sl, 8), dtype=torch.int32, device="cuda")
-    st = torch.cuda.current_stream()
+    st = torch.cuda.Stream()  # a capturable stream (not the legacy default stream)
+    torch.cuda.synchronize()
 
     def slice_pk(s):
         return [pk[j][offs[j][s - 1]:offs[j][s]] for j in range(len(rs))]
 
     # the autotuner picks the batched launch shape on slice 1 (ingesting it)
-    best, _ = sps.sps_autotune_ingest([r.h for r in routers], slice_pk(1), 1)
+    best, _ = sps.sps_autotune_ingest([r.h for r in routers], slice_pk(1), 1, st)
     for r in routers:
         sps.sps_set_tuning(r.h, best["blocks_per_cu"], best["batch_tile"])
     torch.cuda.synchronize()
@@ -134,12 +135,16 @@ def merge_extra(log_fn):
     t0 = time.perf_counter()
     for s in range(2, n_sl + 1):
         sps.sps_graph_begin(st)
-        sps.sps_ingest_batched([r.h for r in routers], slice_pk(s), s, st)
-        if s >= C3_WINDOW:
-            merged.merge(routers, st)
-            sps.sps_scan_async(merged.h, C3_WINDOW, C3_THRESHOLD, res[s - 1], cap, info[s - 1], st)
-        g = sps.sps_graph_end(st)
+        try:
+            sps.sps_ingest_batched([r.h for r in routers], slice_pk(s), s, st)
+            if s >= C3_WINDOW:
+                merged.merge(routers, st)
+                sps.sps_scan_async(merged.h, C3_WINDOW, C3_THRESHOLD, res[s - 1], cap,
+                                   info[s - 1], st)
+        finally:
+            g = sps.sps_graph_end(st)
         sps.sps_graph_launch(g, st)
+        st.synchronize()
         sps.sps_graph_destroy(g)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -151,10 +156,10 @@ def merge_extra(log_fn):
     sps.sps_ingest_batched([r.h for r in routers], slice_pk(n_sl), n_sl, st)
     merged.merge(routers, st)
     sps.sps_scan_async(merged.h, C3_WINDOW, C3_THRESHOLD, res[n_sl - 1], cap, info[n_sl - 1], st)
+    st.synchronize()
     prof = sps.sps_profile_read()
     sps.sps_profile_enable(False)
     inf = info.cpu().numpy()
-    state_bytes = (merged.nbytes)  # device block incl. workspace; state part below
     tau, _, row_len = merged.derived()
     p = C3_PARAMS
     state = 2 * ((p["r"] << p["q"]) * p["eta"] + p["rp"] * row_len)
@@ -321,7 +326,7 @@ def main():
     sps.sps_profile_read()
     step()
     prof_all = sps.sps_profile_read()
-    kernel_stages = ("ingest", "scan_stats", "scan_hot", "join", "estimate", "fill")
+    kernel_stages = ("ingest", "scan_stats", "join", "estimate", "sort", "fill")
     dominant = max(kernel_stages, key=lambda k: prof_all[k][0])
     # timed region: events only around ingests, whole scans and the dominant kernel
     sps.sps_profile_enable(True, stages={"ingest", "scan", dominant})
@@ -341,8 +346,9 @@ def main():
     tau, _, row_len = sk.derived()
     stores_per_pkt = params["rp"] + params["r"] * 2.0 ** -tau
     ingest_bytes_per_pkt = 8 + 2 * stores_per_pkt
-    # the SLE-array stream of a scan (row live counts); the hot-SRE pass is its own stage
-    stats_bytes = 2 * params["rp"] * row_len
+    # a scan's first kernel streams the SLE array and the SRE array once
+    stats_bytes = 2 * (params["rp"] * row_len + (params["r"] << params["q"]) * params["eta"]) \
+        + (params["r"] << params["q"]) // 8
     alg_bytes = {
         "ingest": rec.n_packets / rec.n_slices * ingest_bytes_per_pkt,
         "scan_stats": stats_bytes,
@@ -351,9 +357,8 @@ def main():
                     "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
                 for k, v in prof_all.items() if v[1]}
     avg_s = prof[dominant][0] / prof[dominant][1] / 1e3
-    kernel_names = {"ingest": "k_ingest", "scan_stats": "k_scan_stats (SLE rows)",
-                    "scan_hot": "k_scan_stats (SREs)", "join": "k_join",
-                    "estimate": "k_estimate", "fill": "k_fill_zero"}
+    kernel_names = {"ingest": "k_ingest", "scan_stats": "k_scan_stats", "join": "k_join",
+                    "estimate": "k_estimate", "sort": "k_rank_sort", "fill": "k_fill_zero"}
     if dominant in alg_bytes:
         achieved = alg_bytes[dominant] / avg_s / 1e9
         traffic = stored_traffic(kernel_names[dominant])

@@ -296,11 +296,11 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
 #define SPS_STAGE_SCAN_STATS 5
 #define SPS_STAGE_JOIN 6
 #define SPS_STAGE_ESTIMATE 7
-#define SPS_STAGE_SCAN 8
+#define SPS_STAGE_SORT 8
 #define SPS_STAGE_FEATURES 9
 #define SPS_STAGE_PROBE 10
 #define SPS_STAGE_MLP 11
-#define SPS_STAGE_SCAN_HOT 12
+#define SPS_STAGE_SCAN 12
 #define SPS_NSTAGES 13
 int sps_profile_enable(uint32_t stage_mask);
 int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);

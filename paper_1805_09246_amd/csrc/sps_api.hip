@@ -38,7 +38,6 @@ struct sps_sketch {
   int device;
   int n_cu;
   sps_tuning tune;
-  sps::ScanStreams ss;  // auxiliary stream and fork / join events of the scan
 };
 
 namespace {
@@ -306,14 +305,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
     delete s;
     return SPS_ENOMEM;
   }
-  if (hipStreamCreateWithFlags(&s->ss.aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ss.fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ss.join, hipEventDisableTiming) != hipSuccess) {
-    (void)hipHostFree(s->h_info);
-    if (s->owns) (void)hipFree(s->base);
-    delete s;
-    return hip_fail(hipGetLastError(), "sps_create: scan stream");
-  }
+
   s->bytes = L.total;
   uint8_t* b = static_cast<uint8_t*>(s->base);
   Dev& d = s->dev;
@@ -369,9 +361,7 @@ int sps_destroy(sps_sketch* s) {
   (void)hipDeviceSynchronize();
   if (s->owns) (void)hipFree(s->base);
   (void)hipHostFree(s->h_info);
-  (void)hipEventDestroy(s->ss.fork);
-  (void)hipEventDestroy(s->ss.join);
-  (void)hipStreamDestroy(s->ss.aux);
+
   delete s;
   return SPS_OK;
 }
@@ -590,7 +580,7 @@ int sps_scan_async(sps_sketch* s, uint32_t window, double threshold, sps_result*
   if (s->p.mode == SPS_MODE_DISCRETE && window != 1) return SPS_EINVAL;
   if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
   SPS_HIP(sps::launch_scan(s->dev, s->cur, window, threshold, d_out, (uint32_t)cap, d_info,
-                           s->mlp, s->n_cu, (hipStream_t)stream, s->ss));
+                           s->mlp, s->n_cu, (hipStream_t)stream));
   return SPS_OK;
 }
 

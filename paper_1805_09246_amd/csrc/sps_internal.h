@@ -22,8 +22,7 @@ struct Ctrl {
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
   uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
   unsigned long long join_next;  // next (he0, he1) pair handed out by the join
-  uint32_t blocks_done;       // estimate blocks finished (the last one orders the results)
-  uint32_t pad0;
+  uint32_t pad0[2];
   // copies of the last scan's counters, for inspection (not cleared)
   uint32_t last_row_live[kMaxRP];
   uint32_t last_n_cand;
@@ -117,15 +116,9 @@ hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st);
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
                         uint64_t bytes, bool bits, hipStream_t st);
-// The scan's SLE-array stream runs on `aux` (forked from and joined back to `st` with the
-// two events) beside the hot-SRE pass and the join on `st`.
-struct ScanStreams {
-  hipStream_t aux;
-  hipEvent_t fork, join;
-};
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       int n_cu, hipStream_t st, const ScanStreams& ss);
+                       int n_cu, hipStream_t st);
 hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_stores,
                                 uint32_t seed, uint16_t value, int n_cu, hipStream_t st);
 hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, int n_cu,

@@ -348,11 +348,12 @@ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i
 // lanes stay busy and waves stay balanced.  Every iteration a lane expands one node, backs
 // up one row, or takes a pair.  Tables and hot lists are staged in LDS when they fit.
 constexpr uint32_t kJoinThreads = 1024;
-constexpr uint32_t kJoinChunk = 128;
-constexpr uint32_t kJoinListLds = 6144;
+constexpr uint32_t kJoinChunk = 256;
 
+// list_cap: entries of LDS left for the two hot lists after the table (0: lists stay in
+// global memory).
 template <bool kTbLds>
-__global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
+__global__ void __launch_bounds__(kJoinThreads) k_join(Dev d, uint32_t list_cap) {
   extern __shared__ uint32_t sh[];
   const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
@@ -368,7 +369,7 @@ __global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
     tb = sh;
     off = words;
   }
-  if (n0 + n1 <= kJoinListLds) {  // uniform
+  if (n0 + n1 <= list_cap) {  // uniform
     for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) sh[off + j] = l0[j];
     for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) sh[off + n0 + j] = l1[j];
     l0 = sh + off;
@@ -378,6 +379,7 @@ __global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u, dmask = (1u << dl) - 1u;
   uint64_t pool_next = 0, pool_end = 0;  // the wave's chunk (same value in every lane)
+  uint32_t pa = 0, pb = 0;               // pool_next = pa * n1 + pb
   bool exhausted = false;
   bool done = false, have = false;
   uint32_t he0 = 0, top0 = 0, i = 2, R = 0;
@@ -395,6 +397,8 @@ __global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
         } else {
           pool_next = base;
           pool_end = base + kJoinChunk < pairs ? base + kJoinChunk : pairs;
+          pa = (uint32_t)(base / n1);  // once per chunk, the same in every lane
+          pb = (uint32_t)(base - (uint64_t)pa * n1);
         }
       }
       const uint64_t avail = pool_end - pool_next;
@@ -402,9 +406,11 @@ __global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
           (uint32_t)(need_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
       if (need) {
         if (rank < avail) {
-          const uint64_t p = pool_next + rank;
-          const uint32_t a = (uint32_t)(p / n1);
-          const uint32_t b = (uint32_t)(p - (uint64_t)a * n1);
+          uint32_t a = pa, b = pb + rank;  // rank < 64: step over whole rows of n1
+          while (b >= n1) {
+            b -= n1;
+            ++a;
+          }
           he0 = l0[a];
           top0 = he0 >> (q - dl);
           x = he0 ^ l1[b];
@@ -418,7 +424,13 @@ __global__ void __launch_bounds__(kJoinThreads) k_join(Dev d) {
         }
       }
       const uint64_t taken = (uint64_t)__popcll(need_mask);
-      pool_next += taken < avail ? taken : avail;
+      const uint32_t adv = (uint32_t)(taken < avail ? taken : avail);
+      pool_next += adv;
+      pb += adv;
+      while (pb >= n1) {
+        pb -= n1;
+        ++pa;
+      }
     }
     if (__ballot(!done) == 0) break;
     if (!have || (R == 0u && i == 2u)) continue;
@@ -584,14 +596,18 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
-// Stage 4 (run by the last estimate block): order the kept hosts ascending.  Hosts are
-// distinct, so a host's rank is the number of smaller kept hosts; the block counts over LDS
-// tiles of the list.  Then the info words, the inspection copies, and the working counters
-// cleared for the next scan.
+// Stage 4: order the kept hosts ascending.  Hosts are distinct, so a host's rank is the
+// number of smaller kept hosts, counted over LDS tiles of the list.  One block; it then
+// writes the info words and the inspection copies and clears the working counters for the
+// next scan (the kernel boundary makes every earlier block's results visible, so no
+// device-wide fence is needed).
+constexpr int kSortThreads = 1024;
 constexpr int kSortTile = 4096;
 
-__device__ void order_and_finish(const Dev& d, sps_result* __restrict__ out, uint32_t cap,
-                                 uint32_t* __restrict__ info, uint32_t* tile) {
+__global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
+                                                            uint32_t cap,
+                                                            uint32_t* __restrict__ info) {
+  __shared__ uint32_t tile[kSortTile];
   Ctrl* c = d.ctrl;
   const uint32_t n = min(c->n_kept, d.cand_cap);
   if (out) {
@@ -635,17 +651,13 @@ __device__ void order_and_finish(const Dev& d, sps_result* __restrict__ out, uin
 
 // Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.  With a host
 // list (`hosts` non-null) every host is estimated and written to direct[c] unfiltered.
-// In a scan the blocks first clear the join's table (the join has finished), and the block
-// that finishes last orders the kept hosts into `out` and clears the counters.
+// In a scan the blocks also clear the join's table (the join has finished) for the next
+// scan.
 __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t lo, uint32_t k,
                                                   double threshold, MlpRef mlp,
                                                   const uint32_t* __restrict__ hosts,
                                                   uint32_t n_hosts,
-                                                  sps_result* __restrict__ direct,
-                                                  sps_result* __restrict__ out, uint32_t cap,
-                                                  uint32_t* __restrict__ info) {
-  __shared__ uint32_t tile[kSortTile];
-  __shared__ uint32_t last;
+                                                  sps_result* __restrict__ direct) {
   const uint32_t n = hosts ? n_hosts : min(d.ctrl->n_cand, d.cand_cap);
   const uint32_t* __restrict__ src = hosts ? hosts : d.cand;
   if (!hosts) {
@@ -710,70 +722,55 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       }
     }
   }
-  // the last block to finish sees every block's results
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(&d.ctrl->blocks_done, 1u) == gridDim.x - 1u;
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    order_and_finish(d, out, cap, info, tile);
-  }
 }
 
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       int n_cu, hipStream_t st, const ScanStreams& ss) {
+                       int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // The SLE-array stream (row live counts, HBM bound) only feeds the estimate, and the hot
-  // SREs + join (LDS / ALU bound) do not read it: the stream runs on the auxiliary stream
-  // beside them, with about half of each CU's wave slots, and is joined before the estimate.
+  // SLE rows streamed by about two blocks per CU (grid-stride, four 16-byte non-temporal
+  // loads in flight per lane), then one SRE per lane for the hot SREs
   const uint64_t nvec_row = d.row_stride / 8;
   uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
-  const uint64_t want = ((uint64_t)n_cu * 4 + d.rp - 1) / d.rp;
+  const uint64_t want = ((uint64_t)n_cu * 2 + d.rp - 1) / d.rp;
   if (nb_row > want) nb_row = want;
   if (nb_row < 1) nb_row = 1;
-  hipError_t e = hipEventRecord(ss.fork, st);
-  if (e == hipSuccess) e = hipStreamWaitEvent(ss.aux, ss.fork, 0);
-  if (e != hipSuccess) return e;
-  {
-    ProfScope ps(SPS_STAGE_SCAN_STATS, ss.aux);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row)), dim3(256), 0, ss.aux, d,
-                       lo, (uint32_t)nb_row);
-  }
-  e = hipEventRecord(ss.join, ss.aux);
-  if (e != hipSuccess) return e;
   const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
   {
-    ProfScope ps(SPS_STAGE_SCAN_HOT, st);  // the hot-SRE part: nb_row = 0, SRE blocks only
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)sre_blocks), dim3(256), 0, st, d, lo, 0u);
+    ProfScope ps(SPS_STAGE_SCAN_STATS, st);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row + sre_blocks)), dim3(256),
+                       0, st, d, lo, (uint32_t)nb_row);
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
+    // the transposed table goes to LDS when it fits in half the budget; the hot lists get
+    // whatever LDS is left
     const uint32_t tb_bytes = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
-    const uint32_t list_bytes = kJoinListLds * 4;
-    if (tb_bytes + list_bytes <= kJoinLdsMax)
-      hipLaunchKernelGGL(k_join<true>, dim3(n_cu), dim3(kJoinThreads), tb_bytes + list_bytes,
-                         st, d);
-    else
-      hipLaunchKernelGGL(k_join<false>, dim3(n_cu), dim3(kJoinThreads), list_bytes, st, d);
+    if (tb_bytes <= kJoinLdsMax / 2) {
+      const uint32_t cap_l = (kJoinLdsMax - tb_bytes) / 4;
+      hipLaunchKernelGGL(k_join<true>, dim3(n_cu * 2), dim3(kJoinThreads), tb_bytes + cap_l * 4,
+                         st, d, cap_l);
+    } else {
+      const uint32_t cap_l = kJoinLdsMax / 4;
+      hipLaunchKernelGGL(k_join<false>, dim3(n_cu * 2), dim3(kJoinThreads), cap_l * 4, st, d,
+                         cap_l);
+    }
   }
-  e = hipStreamWaitEvent(st, ss.join, 0);
-  if (e != hipSuccess) return e;
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
     hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
-                       threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr, out,
-                       cap, info);
+                       threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr);
+  }
+  {
+    ProfScope ps(SPS_STAGE_SORT, st);
+    hipLaunchKernelGGL(k_rank_sort, dim3(1), dim3(kSortThreads), 0, st, d, out, cap, info);
   }
   return hipGetLastError();
 }
 
-// Estimates of given hosts: SLE row live counts, then the estimate of every host (its last
-// block clears the counters).
+// Estimates of given hosts: SLE row live counts, then the estimate of every host, then the
+// counters cleared.
 hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const uint32_t* hosts, uint32_t n, sps_result* out,
                                  const MlpRef& mlp, int n_cu, hipStream_t st) {
@@ -789,13 +786,14 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
     hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row)), dim3(256), 0, st, d, lo,
                        (uint32_t)nb_row);
   }
-  if (n == 0) return launch_scan_reset(d, false, st);  // only the counters to clear
-  uint32_t blocks = (n + 3) / 4;
-  if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
-  ProfScope ps(SPS_STAGE_ESTIMATE, st);
-  hipLaunchKernelGGL(k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
-                     hosts, n, out, (sps_result*)nullptr, 0u, (uint32_t*)nullptr);
-  return hipGetLastError();
+  if (n) {
+    uint32_t blocks = (n + 3) / 4;
+    if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
+    ProfScope ps(SPS_STAGE_ESTIMATE, st);
+    hipLaunchKernelGGL(k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
+                       hosts, n, out);
+  }
+  return launch_scan_reset(d, false, st);  // the counters are clear again
 }
 
 // Features only: per-age cumulative union-SLE live counts of given hosts.

@@ -35,7 +35,7 @@ EXPORTS = [
     "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
-          "estimate", "scan", "features", "probe", "mlp", "scan_hot"]
+          "estimate", "sort", "features", "probe", "mlp", "scan"]
 
 
 class sps_tuning(C.Structure):
