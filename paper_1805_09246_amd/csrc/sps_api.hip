@@ -284,6 +284,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   int device = 0, n_cu = 0;
   SPS_HIP(hipGetDevice(&device));
   SPS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+  SPS_HIP(sps::prepare_join());
   sps_sketch* s = new (std::nothrow) sps_sketch();
   if (!s) return SPS_ENOMEM;
   s->p = *p;

@@ -116,6 +116,7 @@ hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st);
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
                         uint64_t bytes, bool bits, hipStream_t st);
+hipError_t prepare_join();  // allows the join its LDS (call before the first scan)
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st);

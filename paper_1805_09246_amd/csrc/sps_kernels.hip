@@ -11,7 +11,6 @@
 namespace sps {
 
 constexpr int kWave = 64;
-constexpr uint32_t kJoinLdsMax = 64u << 10;  // hot bitmaps staged in LDS up to this size
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -223,50 +222,55 @@ __device__ __forceinline__ uint32_t live8(u32x4 v, uint32_t lo) {
   return n;
 }
 
-// Stage 1.  Blocks [0, rp * nb_row) stream the SLE array, one row per block group, and add
-// their live-cell counts to row_live (Def. 4).  The remaining blocks take one SRE per lane:
-// k-weight >= hot cut marks it hot (Sec. 3.3); a wave's 64 verdicts become one ballot word
-// of the hot bitmap, and rows 0 and 1 also append their hot columns to the HSE lists.
-__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t nb_row) {
-  __shared__ uint32_t red[256 / kWave];
+// Stage 1.  Blocks [0, nb_sle) stream the SLE array: every block takes the same share of
+// every row (grid-stride with four 16-byte non-temporal loads in flight per lane), so all
+// blocks carry equal work, and adds its live-cell counts to row_live (Def. 4).  The
+// remaining blocks take one SRE per lane: k-weight >= hot cut marks it hot (Sec. 3.3); a
+// wave's 64 verdicts become one ballot word of the hot bitmap, and rows 0 and 1 also append
+// their hot columns to the HSE lists.
+__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t nb_sle) {
+  __shared__ uint32_t red[kMaxRP][256 / kWave];
   const uint32_t b = blockIdx.x;
-  const uint32_t slea_blocks = d.rp * nb_row;
-  if (b < slea_blocks) {
-    const uint32_t row = b / nb_row, chunk = b % nb_row;
-    const u32x4* rowp = reinterpret_cast<const u32x4*>(d.slea + (uint64_t)row * d.row_stride);
-    const uint64_t nvec = d.row_stride / 8;
-    const uint64_t step = (uint64_t)nb_row * blockDim.x;
-    uint32_t cnt = 0;
-    uint64_t v = (uint64_t)chunk * blockDim.x + threadIdx.x;
-    if (d.mode == SPS_MODE_DISCRETE) {  // bits: a row is row_stride / 128 vectors
-      const u32x4* rowb = reinterpret_cast<const u32x4*>(
-          reinterpret_cast<const uint32_t*>(d.slea) + (uint64_t)row * (d.row_stride >> 5));
-      const uint64_t nvb = d.row_stride >> 7;
-      for (; v < nvb; v += step) {
-        const u32x4 a = __builtin_nontemporal_load(&rowb[v]);
-        cnt += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+  if (b < nb_sle) {
+    const uint64_t step = (uint64_t)nb_sle * blockDim.x;
+    const uint64_t first = (uint64_t)b * blockDim.x + threadIdx.x;
+    const bool bits = d.mode == SPS_MODE_DISCRETE;  // uniform
+    for (uint32_t row = 0; row < d.rp; ++row) {
+      uint32_t cnt = 0;
+      uint64_t v = first;
+      if (bits) {  // one bit per cell: a row is row_stride / 128 vectors
+        const u32x4* rowb = reinterpret_cast<const u32x4*>(
+            reinterpret_cast<const uint32_t*>(d.slea) + (uint64_t)row * (d.row_stride >> 5));
+        const uint64_t nvb = d.row_stride >> 7;
+        for (; v < nvb; v += step) {
+          const u32x4 a = __builtin_nontemporal_load(&rowb[v]);
+          cnt += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+        }
+      } else {
+        const u32x4* rowp =
+            reinterpret_cast<const u32x4*>(d.slea + (uint64_t)row * d.row_stride);
+        const uint64_t nvec = d.row_stride / 8;
+        for (; v + 3 * step < nvec; v += 4 * step) {
+          const u32x4 a = __builtin_nontemporal_load(&rowp[v]);
+          const u32x4 b2 = __builtin_nontemporal_load(&rowp[v + step]);
+          const u32x4 c = __builtin_nontemporal_load(&rowp[v + 2 * step]);
+          const u32x4 e = __builtin_nontemporal_load(&rowp[v + 3 * step]);
+          cnt += live8(a, lo) + live8(b2, lo) + live8(c, lo) + live8(e, lo);
+        }
+        for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
       }
-    } else {
-      for (; v + 3 * step < nvec; v += 4 * step) {  // four independent loads in flight
-        const u32x4 a = __builtin_nontemporal_load(&rowp[v]);
-        const u32x4 b = __builtin_nontemporal_load(&rowp[v + step]);
-        const u32x4 c = __builtin_nontemporal_load(&rowp[v + 2 * step]);
-        const u32x4 e = __builtin_nontemporal_load(&rowp[v + 3 * step]);
-        cnt += live8(a, lo) + live8(b, lo) + live8(c, lo) + live8(e, lo);
-      }
-      for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
+      cnt = wave_sum(cnt);
+      if (lane_id() == 0) red[row][threadIdx.x / kWave] = cnt;
     }
-    cnt = wave_sum(cnt);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < d.rp) {
       uint32_t t = 0;
-      for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[w];
-      atomicAdd(&d.ctrl->row_live[row], t);
+      for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
+      atomicAdd(&d.ctrl->row_live[threadIdx.x], t);
     }
     return;
   }
-  const uint64_t sre_idx = (uint64_t)(b - slea_blocks) * blockDim.x + threadIdx.x;
+  const uint64_t sre_idx = (uint64_t)(b - nb_sle) * blockDim.x + threadIdx.x;
   const uint64_t n_sre = (uint64_t)d.r << d.q;  // multiple of 64 (q >= 6)
   if (sre_idx - lane_id() >= n_sre) return;     // whole wave out of range
   uint32_t w = 0;
@@ -325,7 +329,7 @@ __device__ __forceinline__ uint32_t child_mask(const uint32_t* __restrict__ tb, 
 }
 
 // Extensions t of row i whose bits stay below bit 32 (bit positions [(i-2)delta + q, ...)).
-__device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i) {
+__host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i) {
   const uint32_t sh = (i - 2u) * dl + q;
   const uint32_t width = 1u << dl;
   if (sh >= 32u) return 1u;
@@ -339,55 +343,68 @@ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i
 // bits [(i-2)delta + q, (i-1)delta + q); the overlap of B(i) with B(i-1) holds by
 // construction, so an extension survives when SRE he0 ^ B(i) of row i is hot and no bit at
 // or above 32 is set.  Each node's surviving extensions come from one load of the
-// transposed hot table.  The search is depth first with the partial address as the stack
-// (backing up re-reads the parent's extensions above the child taken).  A full tuple is
-// kept when RHFG[0] of the address is he0.
+// transposed hot table.  A full tuple is kept when RHFG[0] of the address is he0.
 //
-// Work: pairs are handed to waves in chunks from a global counter; inside a wave, lanes
-// whose search ended take the next pairs of the wave's chunk at once (ballot + mbcnt), so
-// lanes stay busy and waves stay balanced.  Every iteration a lane expands one node, backs
-// up one row, or takes a pair.  Tables and hot lists are staged in LDS when they fit.
-constexpr uint32_t kJoinThreads = 1024;
+// Work: every wave runs its own search with a stack of nodes in LDS.  A node is
+// (x, he0, i): the address bits fixed so far, the row-0 SRE and the next row to extend.
+// Each iteration the wave takes up to 64 nodes from the top of its stack, tops the batch
+// up with fresh (he0, he1) pairs when the stack holds fewer than 64 (pairs come in chunks
+// from a global counter), expands all of them at once (one node per lane) and pushes the
+// children; nodes at the last row check their extensions in place.  Children of lanes
+// nearer the top are pushed above the others, so the stack stays ordered by row from
+// bottom to top.  Then a batch that reaches into the nodes of row i takes every node above
+// row i with it, and no row ever holds more than 64 times the extensions one node can have:
+// the stack needs at most 64 * sum_i |extensions of row i| entries (join_stack_cap).
 constexpr uint32_t kJoinChunk = 256;
+constexpr uint32_t kLdsBytes = 160u << 10;  // LDS of one gfx950 compute unit
 
-// list_cap: entries of LDS left for the two hot lists after the table (0: lists stay in
-// global memory).
+__host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __popc(v);
+#else
+  return (uint32_t)__builtin_popcount(v);
+#endif
+}
+
+// Stack entries one wave can need (see above): 64 per possible extension of every row that
+// pushes its children (rows 2 .. r-2; row r-1 checks its tuples in place).
+uint32_t join_stack_cap(uint32_t q, uint32_t r, uint32_t dl) {
+  uint32_t ext = 0;
+  for (uint32_t i = 2; i + 2 <= r; ++i) ext += popc32(fit_mask(q, dl, i));
+  return 64u * (ext ? ext : 1u);
+}
+
 template <bool kTbLds>
-__global__ void __launch_bounds__(kJoinThreads) k_join(Dev d, uint32_t list_cap) {
+__global__ void __launch_bounds__(1024) k_join(Dev d, uint32_t cap) {
   extern __shared__ uint32_t sh[];
   const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
   const uint64_t pairs = (uint64_t)n0 * n1;
   if (pairs == 0) return;
   const uint32_t* __restrict__ tb = d.hot_t;
-  const uint32_t* __restrict__ l0 = d.hse;
-  const uint32_t* __restrict__ l1 = d.hse + (1u << q);
   uint32_t off = 0;
   if (kTbLds) {
     const uint32_t words = (r << q) >> 5;
     for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
     tb = sh;
-    off = words;
-  }
-  if (n0 + n1 <= list_cap) {  // uniform
-    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) sh[off + j] = l0[j];
-    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) sh[off + n0 + j] = l1[j];
-    l0 = sh + off;
-    l1 = sh + off + n0;
+    off = words;  // even: q >= 6
   }
   __syncthreads();
+  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
+  const uint32_t* __restrict__ l0 = d.hse;
+  const uint32_t* __restrict__ l1 = d.hse + (1u << q);
   const uint32_t lane = lane_id();
-  const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u, dmask = (1u << dl) - 1u;
-  uint64_t pool_next = 0, pool_end = 0;  // the wave's chunk (same value in every lane)
+  const uint64_t below_mask = (1ull << lane) - 1ull;
+  const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
+  const uint32_t cbits = dl + 1u;  // a node has at most 2^delta children
+  uint32_t size = 0;               // nodes on this wave's stack (uniform)
+  uint64_t pool_next = 0, pool_end = 0;  // the wave's chunk of pairs (uniform)
   uint32_t pa = 0, pb = 0;               // pool_next = pa * n1 + pb
   bool exhausted = false;
-  bool done = false, have = false;
-  uint32_t he0 = 0, top0 = 0, i = 2, R = 0;
-  uint64_t x = 0;
   for (;;) {
-    const bool need = !done && (!have || (R == 0u && i == 2u));
-    const uint64_t need_mask = __ballot(need);
-    if (need_mask != 0) {
+    const uint32_t popped = size < 64u ? size : 64u;
+    uint32_t take = 0;
+    if (popped < 64u) {
       if (pool_next >= pool_end && !exhausted) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(&d.ctrl->join_next, (unsigned long long)kJoinChunk);
@@ -402,63 +419,98 @@ __global__ void __launch_bounds__(kJoinThreads) k_join(Dev d, uint32_t list_cap)
         }
       }
       const uint64_t avail = pool_end - pool_next;
-      const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-          (uint32_t)(need_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need_mask, 0u));
-      if (need) {
-        if (rank < avail) {
-          uint32_t a = pa, b = pb + rank;  // rank < 64: step over whole rows of n1
-          while (b >= n1) {
-            b -= n1;
-            ++a;
-          }
-          he0 = l0[a];
-          top0 = he0 >> (q - dl);
-          x = he0 ^ l1[b];
-          i = 2;
-          R = child_mask(tb, q, dl, 2, ((uint32_t)(x >> dl) ^ he0) & lowmask, top0) &
-              fit_mask(q, dl, 2);
-          have = true;
-        } else {
-          have = false;
-          done = exhausted;
-        }
-      }
-      const uint64_t taken = (uint64_t)__popcll(need_mask);
-      const uint32_t adv = (uint32_t)(taken < avail ? taken : avail);
-      pool_next += adv;
-      pb += adv;
-      while (pb >= n1) {
-        pb -= n1;
-        ++pa;
-      }
+      take = (uint64_t)(64u - popped) < avail ? 64u - popped : (uint32_t)avail;
     }
-    if (__ballot(!done) == 0) break;
-    if (!have || (R == 0u && i == 2u)) continue;
-    if (R == 0u) {  // extensions of row i exhausted: back up to row i-1
-      --i;
-      const uint32_t s = (i - 2u) * dl + q;
-      const uint32_t t = (uint32_t)(x >> s) & dmask;
-      x &= (1ull << s) - 1ull;
-      R = child_mask(tb, q, dl, i, ((uint32_t)(x >> ((i - 1u) * dl)) ^ he0) & lowmask, top0) &
-          fit_mask(q, dl, i) & ~((2u << t) - 1u);
-    } else {
-      const uint32_t t = (uint32_t)__builtin_ctz(R);
-      R &= R - 1u;
-      const uint64_t xi = x | ((uint64_t)t << ((i - 2u) * dl + q));
-      if (i + 1u == r) {
-        const uint32_t addr = (uint32_t)xi;
+    if (popped + take == 0u) break;  // stack empty and no pairs left
+    uint32_t x = 0, he0 = 0, i = 2, R = 0;
+    if (lane < popped) {
+      const u32x2 nd = stk[size - 1u - lane];
+      x = nd.x;
+      he0 = nd.y & 0xFFFFFFu;
+      i = nd.y >> 24;
+    } else if (lane < popped + take) {
+      uint32_t a = pa, b = pb + (lane - popped);
+      while (b >= n1) {
+        b -= n1;
+        ++a;
+      }
+      he0 = l0[a];
+      x = he0 ^ l1[b];
+    }
+    if (lane < popped + take) {
+      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
+      R = child_mask(tb, q, dl, i, low, he0 >> (q - dl)) & fit_mask(q, dl, i);
+    }
+    const uint32_t sx = (i - 2u) * dl + q;  // first bit of the extension
+    const bool last = i + 1u == r;
+    if (last) {
+      while (R) {
+        const uint32_t t = (uint32_t)__builtin_ctz(R);
+        R &= R - 1u;
+        const uint32_t addr = sx < 32u ? x | (t << sx) : x;
         if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
           const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
           if (pos < d.cand_cap) d.cand[pos] = addr;
         }
-      } else {
-        x = xi;
-        ++i;
-        R = child_mask(tb, q, dl, i, ((uint32_t)(x >> ((i - 1u) * dl)) ^ he0) & lowmask, top0) &
-            fit_mask(q, dl, i);
       }
     }
+    const uint32_t c = popc32(R);  // children to push (0 at the last row)
+    uint32_t below = 0, total = 0;
+    for (uint32_t bit = 0; bit < cbits; ++bit) {
+      const uint64_t m = __ballot((c >> bit) & 1u);
+      below += (uint32_t)__popcll(m & below_mask) << bit;
+      total += (uint32_t)__popcll(m) << bit;
+    }
+    const uint32_t base = size - popped;
+    uint32_t pos = base + total - below;  // this lane's children end here
+    const uint32_t meta = he0 | ((i + 1u) << 24);
+    while (R) {
+      const uint32_t t = (uint32_t)__builtin_ctz(R);
+      R &= R - 1u;
+      const u32x2 child = {sx < 32u ? x | (t << sx) : x, meta};
+      if (--pos < cap) stk[pos] = child;  // always true (the bound above); kept as a guard
+    }
+    size = base + total;
+    pool_next += take;
+    pb += take;
+    while (pb >= n1) {
+      pb -= n1;
+      ++pa;
+    }
   }
+}
+
+// Launch shape of the join: waves per block as the LDS allows (the hot table staged once per
+// block when it is small), blocks to fill every compute unit.
+struct JoinShape {
+  bool tb_lds;
+  uint32_t cap, waves, lds, blocks;
+};
+
+JoinShape join_shape(const Dev& d, int n_cu) {
+  JoinShape s{};
+  s.cap = join_stack_cap(d.q, d.r, d.delta);
+  const uint32_t stack = s.cap * 8u;  // at most 80 KiB under the parameter limits
+  const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
+  s.tb_lds = tb <= (32u << 10) && tb + 4u * stack <= kLdsBytes;
+  const uint32_t room = kLdsBytes - (s.tb_lds ? tb : 0u);
+  s.waves = room / stack;
+  if (s.waves > 8u) s.waves = 8u;
+  if (s.waves < 1u) s.waves = 1u;
+  s.lds = (s.tb_lds ? tb : 0u) + s.waves * stack;
+  uint32_t per_cu = kLdsBytes / s.lds;
+  if (per_cu * s.waves > 16u) per_cu = 16u / s.waves;
+  if (per_cu < 1u) per_cu = 1u;
+  s.blocks = (uint32_t)n_cu * per_cu;
+  return s;
+}
+
+hipError_t prepare_join() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
 }
 
 // Union SLE of host x (Alg. 8): cell z keeps the smallest stamp over the r' rows, i.e. the
@@ -729,33 +781,23 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // SLE rows streamed by about two blocks per CU (grid-stride, four 16-byte non-temporal
-  // loads in flight per lane), then one SRE per lane for the hot SREs
-  const uint64_t nvec_row = d.row_stride / 8;
-  uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
-  const uint64_t want = ((uint64_t)n_cu * 2 + d.rp - 1) / d.rp;
-  if (nb_row > want) nb_row = want;
-  if (nb_row < 1) nb_row = 1;
+  // the SLE array streamed by two blocks per CU, then one SRE per lane for the hot SREs
+  const uint32_t nb_sle = (uint32_t)n_cu * 2u;
   const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
   {
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row + sre_blocks)), dim3(256),
-                       0, st, d, lo, (uint32_t)nb_row);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(nb_sle + sre_blocks)), dim3(256), 0, st,
+                       d, lo, nb_sle);
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
-    // the transposed table goes to LDS when it fits in half the budget; the hot lists get
-    // whatever LDS is left
-    const uint32_t tb_bytes = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
-    if (tb_bytes <= kJoinLdsMax / 2) {
-      const uint32_t cap_l = (kJoinLdsMax - tb_bytes) / 4;
-      hipLaunchKernelGGL(k_join<true>, dim3(n_cu * 2), dim3(kJoinThreads), tb_bytes + cap_l * 4,
-                         st, d, cap_l);
-    } else {
-      const uint32_t cap_l = kJoinLdsMax / 4;
-      hipLaunchKernelGGL(k_join<false>, dim3(n_cu * 2), dim3(kJoinThreads), cap_l * 4, st, d,
-                         cap_l);
-    }
+    const JoinShape js = join_shape(d, n_cu);
+    if (js.tb_lds)
+      hipLaunchKernelGGL(k_join<true>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
+                         js.cap);
+    else
+      hipLaunchKernelGGL(k_join<false>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
+                         js.cap);
   }
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
@@ -775,16 +817,11 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const uint32_t* hosts, uint32_t n, sps_result* out,
                                  const MlpRef& mlp, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
-  const uint64_t nvec_row = d.row_stride / 8;
-  uint64_t nb_row = (nvec_row + 256 * 8 - 1) / (256 * 8);
-  const uint64_t want = ((uint64_t)n_cu * 8 + d.rp - 1) / d.rp;
-  if (nb_row > want) nb_row = want;
-  if (nb_row < 1) nb_row = 1;
   {
     // only the SLE-array blocks: the SRE part of the grid is not launched
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(d.rp * nb_row)), dim3(256), 0, st, d, lo,
-                       (uint32_t)nb_row);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu * 2u), dim3(256), 0, st, d, lo,
+                       (uint32_t)n_cu * 2u);
   }
   if (n) {
     uint32_t blocks = (n + 3) / 4;
