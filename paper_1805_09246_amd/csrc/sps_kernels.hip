@@ -648,21 +648,47 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
-// Stage 4: order the kept hosts ascending.  Hosts are distinct, so a host's rank is the
-// number of smaller kept hosts, counted over LDS tiles of the list.  One block; it then
-// writes the info words and the inspection copies and clears the working counters for the
-// next scan (the kernel boundary makes every earlier block's results visible, so no
-// device-wide fence is needed).
+// Stage 4: order the kept hosts ascending.  Up to kSortTile hosts: a bitonic sort in LDS
+// of (host, index) keys, padded to a power of two with keys above every host.  More: a
+// host's rank is the number of smaller kept hosts (hosts are distinct), counted over LDS
+// tiles of the list.  One block; it then writes the info words and the inspection copies
+// and clears the working counters for the next scan (the kernel boundary makes every
+// earlier block's results visible, so no device-wide fence is needed).
 constexpr int kSortThreads = 1024;
 constexpr int kSortTile = 4096;
 
 __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
                                                             uint32_t cap,
                                                             uint32_t* __restrict__ info) {
-  __shared__ uint32_t tile[kSortTile];
+  __shared__ uint64_t key[kSortTile];
+  uint32_t* const tile = reinterpret_cast<uint32_t*>(key);
   Ctrl* c = d.ctrl;
   const uint32_t n = min(c->n_kept, d.cand_cap);
-  if (out) {
+  if (out && n <= (uint32_t)kSortTile) {
+    uint32_t P = 64;
+    while (P < n) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x)
+      key[i] = i < n ? ((uint64_t)d.kept[i].host << 32) | i : ~0ull;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+          const uint32_t l = i ^ j;
+          if (l > i) {
+            const uint64_t a = key[i], b = key[l];
+            if ((a > b) == ((i & k) == 0)) {
+              key[i] = b;
+              key[l] = a;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t m = n < cap ? n : cap;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
+      out[i] = d.kept[(uint32_t)key[i]];
+  } else if (out) {
     for (uint32_t base = 0; base < n; base += blockDim.x) {
       const uint32_t i = base + threadIdx.x;
       const uint32_t h = i < n ? d.kept[i].host : 0u;
