@@ -348,15 +348,22 @@ __host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, u
 // Work: every wave runs its own search with a stack of nodes in LDS.  A node is
 // (x, he0, i): the address bits fixed so far, the row-0 SRE and the next row to extend.
 // Each iteration the wave takes up to 64 nodes from the top of its stack, tops the batch
-// up with fresh (he0, he1) pairs when the stack holds fewer than 64 (pairs come in chunks
-// from a global counter), expands all of them at once (one node per lane) and pushes the
-// children; nodes at the last row check their extensions in place.  Children of lanes
-// nearer the top are pushed above the others, so the stack stays ordered by row from
-// bottom to top.  Then a batch that reaches into the nodes of row i takes every node above
-// row i with it, and no row ever holds more than 64 times the extensions one node can have:
-// the stack needs at most 64 * sum_i |extensions of row i| entries (join_stack_cap).
-constexpr uint32_t kJoinChunk = 256;
+// up with fresh (he0, he1) pairs when the stack holds fewer than 64, expands all of them at
+// once (one node per lane) and pushes the children; nodes at the last row check their
+// extensions in place.  Children of lanes nearer the top are pushed above the others, so
+// the stack stays ordered by row from bottom to top.  Then a batch that reaches into the
+// nodes of row i takes every node above row i with it, and no row ever holds more than 64
+// times the extensions one node can have: the stack needs at most
+// 64 * sum_i |extensions of row i| entries (join_stack_cap).
+//
+// Pairs are numbered a * n1 + b and cut into groups of 64; wave w of W takes groups w,
+// w + W, w + 2W, ... in order (no shared counter).  Lane j keeps the (a, b) of slot j of the
+// wave's current group; a lane taking a pair reads its coordinates from the owning slot
+// (one cross-lane move), and the next group's are the same advanced by 64 W pairs.  The
+// hot table, the stacks and (when they fit) the two hot lists live in LDS, so the loop
+// touches no global memory except to record a candidate.
 constexpr uint32_t kLdsBytes = 160u << 10;  // LDS of one gfx950 compute unit
+constexpr uint32_t kJoinWaves = 8;         // waves per block at most
 
 __host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
 #ifdef __HIP_DEVICE_COMPILE__
@@ -374,72 +381,88 @@ uint32_t join_stack_cap(uint32_t q, uint32_t r, uint32_t dl) {
   return 64u * (ext ? ext : 1u);
 }
 
-template <bool kTbLds>
-__global__ void __launch_bounds__(1024) k_join(Dev d, uint32_t cap) {
-  extern __shared__ uint32_t sh[];
+// Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (LDS or global).
+template <typename T>
+struct HotLists {
+  const T* l0;
+  const T* l1;
+  __device__ __forceinline__ uint32_t he0(uint32_t a) const { return l0[a]; }
+  __device__ __forceinline__ uint32_t he1(uint32_t b) const { return l1[b]; }
+};
+
+template <bool kTbLds, typename L>
+__device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
+                                          u32x2* __restrict__ stk, uint32_t cap, L lists,
+                                          uint32_t n0, uint32_t n1) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
-  const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
   const uint64_t pairs = (uint64_t)n0 * n1;
-  if (pairs == 0) return;
-  const uint32_t* __restrict__ tb = d.hot_t;
-  uint32_t off = 0;
-  if (kTbLds) {
-    const uint32_t words = (r << q) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
-    tb = sh;
-    off = words;  // even: q >= 6
-  }
-  __syncthreads();
-  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
-  const uint32_t* __restrict__ l0 = d.hse;
-  const uint32_t* __restrict__ l1 = d.hse + (1u << q);
   const uint32_t lane = lane_id();
   const uint64_t below_mask = (1ull << lane) - 1ull;
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
   const uint32_t cbits = dl + 1u;  // a node has at most 2^delta children
-  uint32_t size = 0;               // nodes on this wave's stack (uniform)
-  uint64_t pool_next = 0, pool_end = 0;  // the wave's chunk of pairs (uniform)
-  uint32_t pa = 0, pb = 0;               // pool_next = pa * n1 + pb
-  bool exhausted = false;
+
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
+  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / kWave) + wib;
+  const uint64_t stride = 64ull * n_waves;  // pairs between a wave's groups
+  const uint32_t step_a = (uint32_t)(stride / n1);  // < n0 whenever it is used
+  const uint32_t step_b = (uint32_t)(stride - (uint64_t)step_a * n1);
+  uint64_t g_first = wave * 64ull;  // first pair of the current group (uniform)
+  uint32_t ga = 0, gb = 0;          // this lane's slot of the current group
+  if (g_first < pairs) {
+    const uint64_t p = g_first + lane;
+    ga = (uint32_t)(p / n1);
+    gb = (uint32_t)(p - (uint64_t)ga * n1);
+  }
+  auto group_n = [pairs](uint64_t first) -> uint32_t {
+    return first < pairs ? (pairs - first < 64ull ? (uint32_t)(pairs - first) : 64u) : 0u;
+  };
+  uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
+  uint32_t used = 0;  // pairs of the current group already taken (uniform)
+  uint32_t size = 0;  // nodes on this wave's stack (uniform)
   for (;;) {
     const uint32_t popped = size < 64u ? size : 64u;
-    uint32_t take = 0;
-    if (popped < 64u) {
-      if (pool_next >= pool_end && !exhausted) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&d.ctrl->join_next, (unsigned long long)kJoinChunk);
-        base = __shfl(base, 0, kWave);
-        if (base >= pairs) {
-          exhausted = true;
-        } else {
-          pool_next = base;
-          pool_end = base + kJoinChunk < pairs ? base + kJoinChunk : pairs;
-          pa = (uint32_t)(base / n1);  // once per chunk, the same in every lane
-          pb = (uint32_t)(base - (uint64_t)pa * n1);
-        }
+    const uint32_t need = 64u - popped;
+    const uint32_t t1 = cur_n - used < need ? cur_n - used : need;  // from the current group
+    const uint32_t t2 = nxt_n < need - t1 ? nxt_n : need - t1;      // then from the next
+    if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
+    const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
+    const uint32_t slot = k < t1 ? (used + k) & 63u : (k - t1) & 63u;
+    uint32_t a = __shfl(ga, (int)slot, kWave), b = __shfl(gb, (int)slot, kWave);
+    if (k >= t1) {  // a slot of the next group: 64 W pairs further on
+      a += step_a;
+      b += step_b;
+      if (b >= n1) {
+        b -= n1;
+        ++a;
       }
-      const uint64_t avail = pool_end - pool_next;
-      take = (uint64_t)(64u - popped) < avail ? 64u - popped : (uint32_t)avail;
     }
-    if (popped + take == 0u) break;  // stack empty and no pairs left
     uint32_t x = 0, he0 = 0, i = 2, R = 0;
     if (lane < popped) {
       const u32x2 nd = stk[size - 1u - lane];
       x = nd.x;
       he0 = nd.y & 0xFFFFFFu;
       i = nd.y >> 24;
-    } else if (lane < popped + take) {
-      uint32_t a = pa, b = pb + (lane - popped);
-      while (b >= n1) {
-        b -= n1;
-        ++a;
-      }
-      he0 = l0[a];
-      x = he0 ^ l1[b];
+    } else if (k < t1 + t2) {
+      he0 = lists.he0(a);
+      x = he0 ^ lists.he1(b);
     }
-    if (lane < popped + take) {
+    if (lane < popped + t1 + t2) {
       const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
       R = child_mask(tb, q, dl, i, low, he0 >> (q - dl)) & fit_mask(q, dl, i);
+    }
+    used += t1;
+    if (used == cur_n && nxt_n != 0u) {  // move on to the next group
+      g_first += stride;
+      ga += step_a;
+      gb += step_b;
+      if (gb >= n1) {
+        gb -= n1;
+        ++ga;
+      }
+      cur_n = nxt_n;
+      nxt_n = group_n(g_first + stride);
+      used = t2;
     }
     const uint32_t sx = (i - 2u) * dl + q;  // first bit of the extension
     const bool last = i + 1u == r;
@@ -471,20 +494,52 @@ __global__ void __launch_bounds__(1024) k_join(Dev d, uint32_t cap) {
       if (--pos < cap) stk[pos] = child;  // always true (the bound above); kept as a guard
     }
     size = base + total;
-    pool_next += take;
-    pb += take;
-    while (pb >= n1) {
-      pb -= n1;
-      ++pa;
-    }
   }
 }
 
-// Launch shape of the join: waves per block as the LDS allows (the hot table staged once per
-// block when it is small), blocks to fill every compute unit.
+// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
+template <bool kTbLds>
+__global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
+                                                          uint32_t list_words) {
+  extern __shared__ uint32_t sh[];
+  const uint32_t q = d.q, r = d.r;
+  const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
+  if (n0 == 0u || n1 == 0u) return;
+  const uint32_t* __restrict__ tb = d.hot_t;
+  uint32_t off = 0;
+  if (kTbLds) {
+    const uint32_t words = (r << q) >> 5;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
+    tb = sh;
+    off = words;  // even: q >= 6
+  }
+  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
+  uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
+  const uint32_t* g0 = d.hse;
+  const uint32_t* g1 = d.hse + (1u << q);
+  if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
+    uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
+    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
+    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
+    __syncthreads();
+    join_wave<kTbLds>(d, tb, stk, cap, HotLists<uint16_t>{h, h + n0}, n0, n1);
+  } else if (n0 + n1 <= list_words) {  // u32 lists in LDS
+    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) lw[j] = g0[j];
+    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) lw[n0 + j] = g1[j];
+    __syncthreads();
+    join_wave<kTbLds>(d, tb, stk, cap, HotLists<uint32_t>{lw, lw + n0}, n0, n1);
+  } else {
+    __syncthreads();
+    join_wave<kTbLds>(d, tb, stk, cap, HotLists<uint32_t>{g0, g1}, n0, n1);
+  }
+}
+
+// Launch shape of the join: as many waves per block as the LDS allows (up to 8) after the
+// hot table (when it is small) and a reserve for the hot lists; one block per compute
+// unit.
 struct JoinShape {
   bool tb_lds;
-  uint32_t cap, waves, lds, blocks;
+  uint32_t cap, waves, lds, blocks, list_words;
 };
 
 JoinShape join_shape(const Dev& d, int n_cu) {
@@ -492,16 +547,15 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   s.cap = join_stack_cap(d.q, d.r, d.delta);
   const uint32_t stack = s.cap * 8u;  // at most 80 KiB under the parameter limits
   const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
-  s.tb_lds = tb <= (32u << 10) && tb + 4u * stack <= kLdsBytes;
-  const uint32_t room = kLdsBytes - (s.tb_lds ? tb : 0u);
-  s.waves = room / stack;
-  if (s.waves > 8u) s.waves = 8u;
+  const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
+  s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
+  const uint32_t fixed = s.tb_lds ? tb : 0u;
+  s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
+  if (s.waves > kJoinWaves) s.waves = kJoinWaves;
   if (s.waves < 1u) s.waves = 1u;
-  s.lds = (s.tb_lds ? tb : 0u) + s.waves * stack;
-  uint32_t per_cu = kLdsBytes / s.lds;
-  if (per_cu * s.waves > 16u) per_cu = 16u / s.waves;
-  if (per_cu < 1u) per_cu = 1u;
-  s.blocks = (uint32_t)n_cu * per_cu;
+  s.list_words = (kLdsBytes - fixed - s.waves * stack) / 4u;
+  s.lds = kLdsBytes;
+  s.blocks = (uint32_t)n_cu;
   return s;
 }
 
@@ -820,10 +874,10 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
     const JoinShape js = join_shape(d, n_cu);
     if (js.tb_lds)
       hipLaunchKernelGGL(k_join<true>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
-                         js.cap);
+                         js.cap, js.list_words);
     else
       hipLaunchKernelGGL(k_join<false>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
-                         js.cap);
+                         js.cap, js.list_words);
   }
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
