@@ -308,24 +308,26 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
   }
 }
 
-// Hot extensions of a node (Alg. 4-5 check, in bulk): bit t of the result says whether SRE
-// he0 ^ B(i) of row i is hot for the extension t, where B(i)'s low q-delta bits are `low`
-// xor he0's (already folded into `low`) and its top delta bits are t xor he0's top bits.
-// The transposed table holds, for each (row, low), the 2^delta bits over the top bits; the
-// xor with he0's top bits permutes them (swap blocks of 2^b bits for every set bit b).
-__device__ __forceinline__ uint32_t child_mask(const uint32_t* __restrict__ tb, uint32_t q,
-                                               uint32_t dl, uint32_t row, uint32_t low,
-                                               uint32_t top0) {
+// Hot extensions of a node (Alg. 4-5 check, in bulk).  Row i's SRE for the extension t is
+// he0 ^ B(i): its low q-delta bits are `low` (B(i)'s low bits xor he0's, from bits already
+// fixed) and its top delta bits are u = t ^ top0 (top0: he0's top bits).  The transposed
+// table keeps, for each (row, low), the 2^delta hot bits over u in one entry; the result is
+// that entry, indexed by u (the caller maps u back to t = u ^ top0).
+__device__ __forceinline__ uint32_t hot_tops(const uint32_t* __restrict__ tb, uint32_t q,
+                                             uint32_t dl, uint32_t wmask, uint32_t row,
+                                             uint32_t low) {
   const uint32_t pos = (row << q) + (low << dl);
-  const uint32_t width = 1u << dl;
-  const uint32_t wmask = width == 32u ? 0xFFFFFFFFu : ((1u << width) - 1u);
-  uint32_t m = (tb[pos >> 5] >> (pos & 31u)) & wmask;
-  if (top0 & 1u) m = ((m >> 1) & 0x55555555u) | ((m & 0x55555555u) << 1);
-  if (top0 & 2u) m = ((m >> 2) & 0x33333333u) | ((m & 0x33333333u) << 2);
-  if (top0 & 4u) m = ((m >> 4) & 0x0F0F0F0Fu) | ((m & 0x0F0F0F0Fu) << 4);
-  if (top0 & 8u) m = ((m >> 8) & 0x00FF00FFu) | ((m & 0x00FF00FFu) << 8);
-  if (top0 & 16u) m = (m >> 16) | (m << 16);
-  return m & wmask;
+  return (tb[pos >> 5] >> (pos & 31u)) & wmask;
+}
+
+// The extensions allowed by bit 32 (t < 2^f, see fit_mask) as a mask over u = t ^ top0: a
+// block of 2^f consecutive u values starting at top0 with its low f bits cleared.
+__device__ __forceinline__ uint32_t fit_tops(uint32_t sx, uint32_t dl, uint32_t wmask,
+                                             uint32_t top0) {
+  const uint32_t f = sx >= 32u ? 0u : (32u - sx < dl ? 32u - sx : dl);
+  if (f == dl) return wmask;
+  const uint32_t blk = 1u << f;  // <= 16 here
+  return ((1u << blk) - 1u) << (top0 & ~(blk - 1u));
 }
 
 // Extensions t of row i whose bits stay below bit 32 (bit positions [(i-2)delta + q, ...)).
@@ -381,7 +383,7 @@ uint32_t join_stack_cap(uint32_t q, uint32_t r, uint32_t dl) {
   return 64u * (ext ? ext : 1u);
 }
 
-// Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (LDS or global).
+// Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (global).
 template <typename T>
 struct HotLists {
   const T* l0;
@@ -390,30 +392,55 @@ struct HotLists {
   __device__ __forceinline__ uint32_t he1(uint32_t b) const { return l1[b]; }
 };
 
-template <bool kTbLds, typename L>
+// a = p / n1, b = p % n1 from a double-precision estimate corrected by one step (the
+// estimate is off by less than one: p < 2^48 and rcp = 1/n1 to 53 bits).
+template <bool kSmall>
+__device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp, uint32_t& a,
+                                            uint32_t& b) {
+  if (kSmall) {  // p < 2^32
+    const uint32_t p32 = (uint32_t)p;
+    uint32_t q0 = (uint32_t)((double)p32 * rcp);
+    int32_t rem = (int32_t)(p32 - q0 * n1);
+    if (rem < 0) {
+      --q0;
+      rem += (int32_t)n1;
+    } else if ((uint32_t)rem >= n1) {
+      ++q0;
+      rem -= (int32_t)n1;
+    }
+    a = q0;
+    b = (uint32_t)rem;
+  } else {
+    uint64_t q0 = (uint64_t)((double)p * rcp);
+    int64_t rem = (int64_t)(p - q0 * n1);
+    if (rem < 0) {
+      --q0;
+      rem += n1;
+    } else if ((uint64_t)rem >= n1) {
+      ++q0;
+      rem -= n1;
+    }
+    a = (uint32_t)q0;
+    b = (uint32_t)rem;
+  }
+}
+
+template <bool kSmall, typename L>
 __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
                                           u32x2* __restrict__ stk, uint32_t cap, L lists,
                                           uint32_t n0, uint32_t n1) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint64_t pairs = (uint64_t)n0 * n1;
   const uint32_t lane = lane_id();
-  const uint64_t below_mask = (1ull << lane) - 1ull;
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
   const uint32_t cbits = dl + 1u;  // a node has at most 2^delta children
+  const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
+  const double rcp = 1.0 / (double)n1;
 
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
   const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / kWave) + wib;
   const uint64_t stride = 64ull * n_waves;  // pairs between a wave's groups
-  const uint32_t step_a = (uint32_t)(stride / n1);  // < n0 whenever it is used
-  const uint32_t step_b = (uint32_t)(stride - (uint64_t)step_a * n1);
-  uint64_t g_first = wave * 64ull;  // first pair of the current group (uniform)
-  uint32_t ga = 0, gb = 0;          // this lane's slot of the current group
-  if (g_first < pairs) {
-    const uint64_t p = g_first + lane;
-    ga = (uint32_t)(p / n1);
-    gb = (uint32_t)(p - (uint64_t)ga * n1);
-  }
+  uint64_t g_first = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + wib) * 64ull;
   auto group_n = [pairs](uint64_t first) -> uint32_t {
     return first < pairs ? (pairs - first < 64ull ? (uint32_t)(pairs - first) : 64u) : 0u;
   };
@@ -427,16 +454,6 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     const uint32_t t2 = nxt_n < need - t1 ? nxt_n : need - t1;      // then from the next
     if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
     const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
-    const uint32_t slot = k < t1 ? (used + k) & 63u : (k - t1) & 63u;
-    uint32_t a = __shfl(ga, (int)slot, kWave), b = __shfl(gb, (int)slot, kWave);
-    if (k >= t1) {  // a slot of the next group: 64 W pairs further on
-      a += step_a;
-      b += step_b;
-      if (b >= n1) {
-        b -= n1;
-        ++a;
-      }
-    }
     uint32_t x = 0, he0 = 0, i = 2, R = 0;
     if (lane < popped) {
       const u32x2 nd = stk[size - 1u - lane];
@@ -444,31 +461,29 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       he0 = nd.y & 0xFFFFFFu;
       i = nd.y >> 24;
     } else if (k < t1 + t2) {
+      const uint64_t pidx = k < t1 ? g_first + used + k : g_first + stride + (k - t1);
+      uint32_t a, b;
+      pair_coords<kSmall>(pidx, n1, rcp, a, b);
       he0 = lists.he0(a);
       x = he0 ^ lists.he1(b);
     }
+    const uint32_t top0 = he0 >> (q - dl);
+    const uint32_t sx = __umul24(i - 2u, dl) + q;  // first bit of the extension
     if (lane < popped + t1 + t2) {
-      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
-      R = child_mask(tb, q, dl, i, low, he0 >> (q - dl)) & fit_mask(q, dl, i);
+      const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
+      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sx, dl, wmask, top0);
     }
     used += t1;
     if (used == cur_n && nxt_n != 0u) {  // move on to the next group
       g_first += stride;
-      ga += step_a;
-      gb += step_b;
-      if (gb >= n1) {
-        gb -= n1;
-        ++ga;
-      }
       cur_n = nxt_n;
       nxt_n = group_n(g_first + stride);
       used = t2;
     }
-    const uint32_t sx = (i - 2u) * dl + q;  // first bit of the extension
     const bool last = i + 1u == r;
     if (last) {
       while (R) {
-        const uint32_t t = (uint32_t)__builtin_ctz(R);
+        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
         const uint32_t addr = sx < 32u ? x | (t << sx) : x;
         if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
@@ -481,14 +496,15 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     uint32_t below = 0, total = 0;
     for (uint32_t bit = 0; bit < cbits; ++bit) {
       const uint64_t m = __ballot((c >> bit) & 1u);
-      below += (uint32_t)__popcll(m & below_mask) << bit;
+      below += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << bit;
       total += (uint32_t)__popcll(m) << bit;
     }
     const uint32_t base = size - popped;
     uint32_t pos = base + total - below;  // this lane's children end here
     const uint32_t meta = he0 | ((i + 1u) << 24);
     while (R) {
-      const uint32_t t = (uint32_t)__builtin_ctz(R);
+      const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
       R &= R - 1u;
       const u32x2 child = {sx < 32u ? x | (t << sx) : x, meta};
       if (--pos < cap) stk[pos] = child;  // always true (the bound above); kept as a guard
@@ -517,20 +533,24 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
+  const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull;
   if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
     uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
     for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
     for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
     __syncthreads();
-    join_wave<kTbLds>(d, tb, stk, cap, HotLists<uint16_t>{h, h + n0}, n0, n1);
-  } else if (n0 + n1 <= list_words) {  // u32 lists in LDS
-    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) lw[j] = g0[j];
-    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) lw[n0 + j] = g1[j];
-    __syncthreads();
-    join_wave<kTbLds>(d, tb, stk, cap, HotLists<uint32_t>{lw, lw + n0}, n0, n1);
+    const HotLists<uint16_t> L{h, h + n0};
+    if (small)
+      join_wave<true>(d, tb, stk, cap, L, n0, n1);
+    else
+      join_wave<false>(d, tb, stk, cap, L, n0, n1);
   } else {
     __syncthreads();
-    join_wave<kTbLds>(d, tb, stk, cap, HotLists<uint32_t>{g0, g1}, n0, n1);
+    const HotLists<uint32_t> L{g0, g1};
+    if (small)
+      join_wave<true>(d, tb, stk, cap, L, n0, n1);
+    else
+      join_wave<false>(d, tb, stk, cap, L, n0, n1);
   }
 }
 
