@@ -223,7 +223,7 @@ __device__ __forceinline__ uint32_t live8(u32x4 v, uint32_t lo) {
 }
 
 // Stage 1.  Blocks [0, nb_sle) stream the SLE array: every block takes the same share of
-// every row (grid-stride with four 16-byte non-temporal loads in flight per lane), so all
+// every row (grid-stride with eight 16-byte non-temporal loads in flight per lane), so all
 // blocks carry equal work, and adds its live-cell counts to row_live (Def. 4).  The
 // remaining blocks take one SRE per lane: k-weight >= hot cut marks it hot (Sec. 3.3); a
 // wave's 64 verdicts become one ballot word of the hot bitmap, and rows 0 and 1 also append
@@ -250,12 +250,12 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
         const u32x4* rowp =
             reinterpret_cast<const u32x4*>(d.slea + (uint64_t)row * d.row_stride);
         const uint64_t nvec = d.row_stride / 8;
-        for (; v + 3 * step < nvec; v += 4 * step) {
-          const u32x4 a = __builtin_nontemporal_load(&rowp[v]);
-          const u32x4 b2 = __builtin_nontemporal_load(&rowp[v + step]);
-          const u32x4 c = __builtin_nontemporal_load(&rowp[v + 2 * step]);
-          const u32x4 e = __builtin_nontemporal_load(&rowp[v + 3 * step]);
-          cnt += live8(a, lo) + live8(b2, lo) + live8(c, lo) + live8(e, lo);
+        for (; v + 7 * step < nvec; v += 8 * step) {  // eight independent loads in flight
+          u32x4 a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&rowp[v + u * step]);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) cnt += live8(a[u], lo);
         }
         for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
       }
@@ -881,8 +881,8 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // the SLE array streamed by two blocks per CU, then one SRE per lane for the hot SREs
-  const uint32_t nb_sle = (uint32_t)n_cu * 2u;
+  // the SLE array streamed by one block per CU, then one SRE per lane for the hot SREs
+  const uint32_t nb_sle = (uint32_t)n_cu;
   const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
   {
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
@@ -920,8 +920,8 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
   {
     // only the SLE-array blocks: the SRE part of the grid is not launched
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu * 2u), dim3(256), 0, st, d, lo,
-                       (uint32_t)n_cu * 2u);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo,
+                       (uint32_t)n_cu);
   }
   if (n) {
     uint32_t blocks = (n + 3) / 4;
