@@ -353,10 +353,13 @@ __host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, u
 // up with fresh (he0, he1) pairs when the stack holds fewer than 64, expands all of them at
 // once (one node per lane) and pushes the children; nodes at the last row check their
 // extensions in place.  Children of lanes nearer the top are pushed above the others, so
-// the stack stays ordered by row from bottom to top.  Then a batch that reaches into the
-// nodes of row i takes every node above row i with it, and no row ever holds more than 64
-// times the extensions one node can have: the stack needs at most
-// 64 * sum_i |extensions of row i| entries (join_stack_cap).
+// the stack stays ordered by row from bottom to top and stays small: a batch that reaches
+// into the nodes of row i takes every node above row i with it, so no row holds more than
+// 64 times the extensions of one node.  That bound (64 * sum_i |extensions of row i|, 2048
+// entries at q = 14, delta = 2) would cost so much LDS that few waves fit on a compute unit,
+// so the stack is smaller (join_stack_entries); when a batch's children do not fit, each
+// lane instead searches its own node's subtree depth first in registers (join_lane_dfs)
+// and nothing is pushed.  Either way every node is expanded exactly once.
 //
 // Pairs are numbered a * n1 + b and cut into groups of 64; wave w of W takes groups w,
 // w + W, w + 2W, ... in order (no shared counter).  Lane j keeps the (a, b) of slot j of the
@@ -365,7 +368,7 @@ __host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, u
 // hot table, the stacks and (when they fit) the two hot lists live in LDS, so the loop
 // touches no global memory except to record a candidate.
 constexpr uint32_t kLdsBytes = 160u << 10;  // LDS of one gfx950 compute unit
-constexpr uint32_t kJoinWaves = 8;         // waves per block at most
+constexpr uint32_t kJoinWaves = 16;        // waves per block at most
 
 __host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
 #ifdef __HIP_DEVICE_COMPILE__
@@ -375,12 +378,11 @@ __host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
 #endif
 }
 
-// Stack entries one wave can need (see above): 64 per possible extension of every row that
-// pushes its children (rows 2 .. r-2; row r-1 checks its tuples in place).
-uint32_t join_stack_cap(uint32_t q, uint32_t r, uint32_t dl) {
-  uint32_t ext = 0;
-  for (uint32_t i = 2; i + 2 <= r; ++i) ext += popc32(fit_mask(q, dl, i));
-  return 64u * (ext ? ext : 1u);
+// Stack entries per wave: room for a full batch of children (64 nodes x 2^delta) on top of
+// what the stack usually holds.
+uint32_t join_stack_entries(uint32_t dl) {
+  const uint32_t need = 64u * (1u << dl) + 64u;
+  return need > 768u ? need : 768u;
 }
 
 // Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (global).
@@ -422,6 +424,49 @@ __device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp,
     }
     a = (uint32_t)q0;
     b = (uint32_t)rem;
+  }
+}
+
+// Subtree search of one lane, with the partial address as its only state: used when a
+// wave's stack has no room for a batch's children.  (x, he0, i) is a node whose row-i
+// extensions (over u = t ^ top0) are R; every descendant is visited once, depth first:
+// backing up from row i to row i-1 clears row i-1's extension bits from x and recomputes
+// row i-1's extensions above the one just finished.
+__device__ __noinline__ void join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
+                                           uint32_t wmask, uint32_t lowmask, uint32_t qmask,
+                                           uint32_t x, uint32_t he0, uint32_t i, uint32_t R) {
+  const uint32_t q = d.q, dl = d.delta, r = d.r;
+  const uint32_t top0 = he0 >> (q - dl), dmask = (1u << dl) - 1u;
+  const uint32_t i0 = i;
+  for (;;) {
+    if (R == 0u) {
+      if (i == i0) return;
+      --i;  // back up: the extension taken at row i
+      const uint32_t sx = (i - 2u) * dl + q;
+      const uint32_t t = sx < 32u ? (x >> sx) & dmask : 0u;
+      if (sx < 32u) x &= (1u << sx) - 1u;
+      const uint32_t u = t ^ top0;
+      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
+      const uint32_t above = u >= 31u ? 0u : ~((2u << u) - 1u);
+      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sx, dl, wmask, top0) & above;
+      continue;
+    }
+    const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+    R &= R - 1u;
+    const uint32_t sx = (i - 2u) * dl + q;
+    const uint32_t xi = sx < 32u ? x | (t << sx) : x;
+    if (i + 1u == r) {
+      if ((fmix32(xi ^ d.seed_rhfg0) & qmask) == he0) {
+        const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+        if (pos < d.cand_cap) d.cand[pos] = xi;
+      }
+    } else {
+      x = xi;
+      ++i;
+      const uint32_t sxn = (i - 2u) * dl + q;
+      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
+      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sxn, dl, wmask, top0);
+    }
   }
 }
 
@@ -501,15 +546,20 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       total += (uint32_t)__popcll(m) << bit;
     }
     const uint32_t base = size - popped;
-    uint32_t pos = base + total - below;  // this lane's children end here
-    const uint32_t meta = he0 | ((i + 1u) << 24);
-    while (R) {
-      const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
-      R &= R - 1u;
-      const u32x2 child = {sx < 32u ? x | (t << sx) : x, meta};
-      if (--pos < cap) stk[pos] = child;  // always true (the bound above); kept as a guard
+    if (base + total <= cap) {  // uniform: the children fit on the stack
+      uint32_t pos = base + total - below;  // this lane's children end here
+      const uint32_t meta = he0 | ((i + 1u) << 24);
+      while (R) {
+        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+        R &= R - 1u;
+        const u32x2 child = {sx < 32u ? x | (t << sx) : x, meta};
+        stk[--pos] = child;
+      }
+      size = base + total;
+    } else {  // no room: every lane searches its own node's subtree depth-first instead
+      join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+      size = base;
     }
-    size = base + total;
   }
 }
 
@@ -554,7 +604,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   }
 }
 
-// Launch shape of the join: as many waves per block as the LDS allows (up to 8) after the
+// Launch shape of the join: as many waves per block as the LDS allows (up to 16) after the
 // hot table (when it is small) and a reserve for the hot lists; one block per compute
 // unit.
 struct JoinShape {
@@ -564,8 +614,8 @@ struct JoinShape {
 
 JoinShape join_shape(const Dev& d, int n_cu) {
   JoinShape s{};
-  s.cap = join_stack_cap(d.q, d.r, d.delta);
-  const uint32_t stack = s.cap * 8u;  // at most 80 KiB under the parameter limits
+  s.cap = join_stack_entries(d.delta);
+  const uint32_t stack = s.cap * 8u;  // at most 16.5 KiB
   const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
   const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;

@@ -267,3 +267,21 @@ def test_c2_full_size():
             got = assert_scan_equal(g, o, C2_WINDOW, C2_THRESHOLD, f"c2 scan at {s}")
             print(f"[c2] slice {s}: state equal, {len(got)} hosts", flush=True)
     g.close()
+
+
+def test_join_dense_rows_stack_fallback():
+    """Rows about a quarter hot at q = 6, delta = 5 (32 extensions per node): the candidate
+    search outgrows a wave's LDS stack, so batches fall back to per-lane depth-first search;
+    candidates and results still match the oracle's exhaustive search."""
+    params = dict(q=6, r=8, delta=5, eta=8, qp=8, rp=2, etap=64, deltap=64, theta=64,
+                  anet_side=0, seed=77)
+    rng = np.random.default_rng(5)
+    n = 2 * 64 * 8
+    hosts = rng.integers(0, 1 << 32, 40, dtype=np.uint64).astype(np.uint32)
+    p = rng.integers(0, 1 << 32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    p[: n // 2, 1] = hosts[rng.integers(0, 40, n // 2)]
+    g, o = sps.Sketch(params), oracle.OracleSketch(params)
+    g.ingest(dev_pkts(p), 1)
+    o.ingest(p, 1)
+    assert_scan_equal(g, o, 1, 64.0, "dense rows")
+    assert len(gpu_candidates(g)) > 10000
