@@ -54,6 +54,8 @@ extern "C" {
 #define SPS_INFO_FLAGS 2     /* bit 0: candidate buffer overflow; bit 1: result buffer overflow */
 #define SPS_INFO_HSE0 3      /* hot SREs in row 0 */
 #define SPS_INFO_HSE1 4      /* hot SREs in row 1 */
+#define SPS_INFO_NODES_LO 5  /* candidate-search nodes expanded (low 32 bits; Alg. 4-5 tuples */
+#define SPS_INFO_NODES_HI 6  /*   grown by one row, (he0, he1) pairs included); high 32 bits */
 #define SPS_INFO_WORDS 8
 
 /* One IP pair as the 8-byte record the paper buffers per packet (Sec. 3.3): (src, dst). */

@@ -21,7 +21,7 @@ struct Ctrl {
   uint32_t hse_count[2];      // hot SREs found in rows 0 and 1
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
   uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
-  unsigned long long join_next;  // next (he0, he1) pair handed out by the join
+  unsigned long long join_nodes;  // nodes the candidate search expanded
   uint32_t pad0[2];
   // copies of the last scan's counters, for inspection (not cleared)
   uint32_t last_row_live[kMaxRP];

@@ -432,15 +432,16 @@ __device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp,
 // extensions (over u = t ^ top0) are R; every descendant is visited once, depth first:
 // backing up from row i to row i-1 clears row i-1's extension bits from x and recomputes
 // row i-1's extensions above the one just finished.
-__device__ __noinline__ void join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
-                                           uint32_t wmask, uint32_t lowmask, uint32_t qmask,
-                                           uint32_t x, uint32_t he0, uint32_t i, uint32_t R) {
+__device__ __noinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
+                                               uint32_t wmask, uint32_t lowmask, uint32_t qmask,
+                                               uint32_t x, uint32_t he0, uint32_t i, uint32_t R) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint32_t top0 = he0 >> (q - dl), dmask = (1u << dl) - 1u;
   const uint32_t i0 = i;
+  uint32_t expanded = 0;  // nodes expanded below (x, he0, i)
   for (;;) {
     if (R == 0u) {
-      if (i == i0) return;
+      if (i == i0) return expanded;
       --i;  // back up: the extension taken at row i
       const uint32_t sx = (i - 2u) * dl + q;
       const uint32_t t = sx < 32u ? (x >> sx) & dmask : 0u;
@@ -463,6 +464,7 @@ __device__ __noinline__ void join_lane_dfs(const Dev& d, const uint32_t* __restr
     } else {
       x = xi;
       ++i;
+      ++expanded;
       const uint32_t sxn = (i - 2u) * dl + q;
       const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
       R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sxn, dl, wmask, top0);
@@ -492,12 +494,14 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
   uint32_t used = 0;  // pairs of the current group already taken (uniform)
   uint32_t size = 0;  // nodes on this wave's stack (uniform)
+  unsigned long long nodes = 0;  // nodes this wave expanded (uniform)
   for (;;) {
     const uint32_t popped = size < 64u ? size : 64u;
     const uint32_t need = 64u - popped;
     const uint32_t t1 = cur_n - used < need ? cur_n - used : need;  // from the current group
     const uint32_t t2 = nxt_n < need - t1 ? nxt_n : need - t1;      // then from the next
     if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
+    nodes += popped + t1 + t2;
     const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
     uint32_t x = 0, he0 = 0, i = 2, R = 0;
     if (lane < popped) {
@@ -556,11 +560,13 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
         stk[--pos] = child;
       }
       size = base + total;
-    } else {  // no room: every lane searches its own node's subtree depth-first instead
-      join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+    } else {  // no room: every lane searches its own node's subtree depth first instead
+      const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+      nodes += wave_sum(e);
       size = base;
     }
   }
+  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, nodes);
 }
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
@@ -772,8 +778,9 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
-// Stage 4: order the kept hosts ascending.  Up to kSortTile hosts: a bitonic sort in LDS
-// of (host, index) keys, padded to a power of two with keys above every host.  More: a
+// Stage 4: order the kept hosts ascending.  Up to kSortTile hosts: a bitonic sort of (host,
+// index) keys, padded to a power of two with keys above every host (in registers and
+// cross-lane moves up to 1024 hosts, in LDS beyond).  More: a
 // host's rank is the number of smaller kept hosts (hosts are distinct), counted over LDS
 // tiles of the list.  One block; it then writes the info words and the inspection copies
 // and clears the working counters for the next scan (the kernel boundary makes every
@@ -788,7 +795,33 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
   uint32_t* const tile = reinterpret_cast<uint32_t*>(key);
   Ctrl* c = d.ctrl;
   const uint32_t n = min(c->n_kept, d.cand_cap);
-  if (out && n <= (uint32_t)kSortTile) {
+  if (out && n <= (uint32_t)kSortThreads) {
+    // one key per thread; partners closer than 64 are in the same wave (cross-lane moves),
+    // farther ones go through LDS
+    uint32_t P = 64;
+    while (P < n) P <<= 1;
+    const uint32_t i = threadIdx.x;
+    uint64_t v = i < n ? ((uint64_t)d.kept[i].host << 32) | i : ~0ull;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        uint64_t w;
+        if (j >= 64u) {
+          __syncthreads();  // the previous stage's readers are done
+          key[i] = v;
+          __syncthreads();
+          w = key[i ^ j];
+        } else {
+          const uint32_t lo = __shfl_xor((uint32_t)v, (int)j, kWave);
+          const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), (int)j, kWave);
+          w = ((uint64_t)hi << 32) | lo;
+        }
+        const bool up = (i & k) == 0u, lower = (i & j) == 0u;
+        v = (lower == up) ? (v < w ? v : w) : (v < w ? w : v);
+      }
+    }
+    const uint32_t m = n < cap ? n : cap;
+    if (i < m) out[i] = d.kept[(uint32_t)v];
+  } else if (out && n <= (uint32_t)kSortTile) {
     uint32_t P = 64;
     while (P < n) P <<= 1;
     for (uint32_t i = threadIdx.x; i < P; i += blockDim.x)
@@ -837,8 +870,8 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
       info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
       info[SPS_INFO_HSE0] = c->hse_count[0];
       info[SPS_INFO_HSE1] = c->hse_count[1];
-      info[5] = 0;
-      info[6] = 0;
+      info[SPS_INFO_NODES_LO] = (uint32_t)c->join_nodes;
+      info[SPS_INFO_NODES_HI] = (uint32_t)(c->join_nodes >> 32);
       info[7] = 0;
     }
     for (uint32_t i = 0; i < (uint32_t)kMaxRP; ++i) c->last_row_live[i] = c->row_live[i];
@@ -1026,16 +1059,16 @@ __global__ void __launch_bounds__(256) k_probe_scatter(uint16_t* __restrict__ ce
 
 __global__ void __launch_bounds__(256) k_probe_stream(const u32x4* __restrict__ buf,
                                                       uint64_t nvec, uint32_t* sum) {
+  // the scan's SLE access shape: grid-stride, eight 16-byte non-temporal loads per lane
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t acc = 0;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < nvec; i += 4 * stride) {
-    const u32x4 a = __builtin_nontemporal_load(&buf[i]);
-    const u32x4 b = __builtin_nontemporal_load(&buf[i + stride]);
-    const u32x4 c = __builtin_nontemporal_load(&buf[i + 2 * stride]);
-    const u32x4 e = __builtin_nontemporal_load(&buf[i + 3 * stride]);
-    acc += (a.x ^ a.y ^ a.z ^ a.w) + (b.x ^ b.y ^ b.z ^ b.w) + (c.x ^ c.y ^ c.z ^ c.w) +
-           (e.x ^ e.y ^ e.z ^ e.w);
+  for (; i + 7 * stride < nvec; i += 8 * stride) {
+    u32x4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(&buf[i + u * stride]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
   }
   for (; i < nvec; i += stride) {
     const u32x4 v = __builtin_nontemporal_load(&buf[i]);
@@ -1057,7 +1090,7 @@ hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_st
 hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, int n_cu,
                                hipStream_t st) {
   ProfScope ps(SPS_STAGE_PROBE, st);
-  hipLaunchKernelGGL(k_probe_stream, dim3(n_cu * 8), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_probe_stream, dim3(n_cu), dim3(256), 0, st,
                      reinterpret_cast<const u32x4*>(buf), bytes / 16, sum);
   return hipGetLastError();
 }

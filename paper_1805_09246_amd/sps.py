@@ -20,6 +20,7 @@ SPS_OK, SPS_EINVAL, SPS_ESLICE, SPS_EMISMATCH = 0, -1, -2, -3
 SPS_ENOMEM, SPS_ECAPACITY, SPS_EHIP, SPS_EBUDGET = -4, -5, -6, -7
 F_SATURATED, F_LC_FALLBACK, F_MLP, F_NEAR, F_CLAMPLOW = 1, 2, 4, 8, 16
 INFO_KEPT, INFO_CAND, INFO_FLAGS, INFO_HSE0, INFO_HSE1, INFO_WORDS = 0, 1, 2, 3, 4, 8
+INFO_NODES_LO, INFO_NODES_HI = 5, 6
 MLP_IN, MLP_HIDDEN = 10, 64
 MLP_PARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 HEADER_BYTES = 64

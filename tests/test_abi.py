@@ -66,3 +66,23 @@ def test_strerror(L):
     for code in range(0, -8, -1):
         assert len(L.strerror(code)) >= 2
     assert L.strerror(-99) == "unknown error"
+
+
+def test_binding_constants_match_header():
+    """Every numeric #define of include/sps.h that the binding mirrors has the same value."""
+    from paper_1805_09246_amd import sps
+    text = open(os.path.join(ROOT, "include", "sps.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in
+            re.finditer(r"^#define SPS_(\w+) \(?(-?\d+)u?\)?", text, re.M)}
+    pairs = {f"SPS_{k}": v for k, v in defs.items() if k.startswith("E") or k == "OK"}
+    pairs.update({k: v for k, v in defs.items() if k.startswith(("F_", "INFO_", "MODE_"))})
+    pairs.update({k: v for k, v in defs.items() if k in ("MLP_IN", "MLP_HIDDEN")})
+    checked = 0
+    for name, v in pairs.items():
+        assert hasattr(sps, name), name
+        assert getattr(sps, name) == v, name
+        checked += 1
+    assert checked >= 20
+    stages = {k[len("STAGE_"):].lower(): v for k, v in defs.items() if k.startswith("STAGE_")}
+    assert stages == {n: j for j, n in enumerate(sps.STAGES)}
+    assert defs["NSTAGES"] == len(sps.STAGES)
