@@ -222,9 +222,9 @@ __device__ __forceinline__ uint32_t live8(u32x4 v, uint32_t lo) {
   return n;
 }
 
-// Stage 1.  Blocks [0, nb_sle) stream the SLE array: every block takes the same share of
-// every row (grid-stride with eight 16-byte non-temporal loads in flight per lane), so all
-// blocks carry equal work, and adds its live-cell counts to row_live (Def. 4).  The
+// Stage 1.  Blocks [0, nb_sle) stream the SLE array as one flat range (grid-stride with eight
+// 16-byte non-temporal loads in flight per lane), so all blocks carry equal work, and add
+// their per-row live-cell counts to row_live (Def. 4).  The
 // remaining blocks take one SRE per lane: k-weight >= hot cut marks it hot (Sec. 3.3); a
 // wave's 64 verdicts become one ballot word of the hot bitmap, and rows 0 and 1 also append
 // their hot columns to the HSE lists.
@@ -234,33 +234,66 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
   if (b < nb_sle) {
     const uint64_t step = (uint64_t)nb_sle * blockDim.x;
     const uint64_t first = (uint64_t)b * blockDim.x + threadIdx.x;
-    const bool bits = d.mode == SPS_MODE_DISCRETE;  // uniform
-    for (uint32_t row = 0; row < d.rp; ++row) {
-      uint32_t cnt = 0;
-      uint64_t v = first;
-      if (bits) {  // one bit per cell: a row is row_stride / 128 vectors
+    uint32_t cnt[kMaxRP];
+#pragma unroll
+    for (int j = 0; j < kMaxRP; ++j) cnt[j] = 0;
+    auto add_to = [&cnt](uint32_t row, uint32_t c) {
+#pragma unroll
+      for (int j = 0; j < kMaxRP; ++j)
+        if ((uint32_t)j == row) cnt[j] += c;
+    };
+    if (d.mode == SPS_MODE_DISCRETE) {  // one bit per cell: a row is row_stride / 128 vectors
+      for (uint32_t row = 0; row < d.rp; ++row) {
         const u32x4* rowb = reinterpret_cast<const u32x4*>(
             reinterpret_cast<const uint32_t*>(d.slea) + (uint64_t)row * (d.row_stride >> 5));
         const uint64_t nvb = d.row_stride >> 7;
-        for (; v < nvb; v += step) {
+        uint32_t c = 0;
+        for (uint64_t v = first; v < nvb; v += step) {
           const u32x4 a = __builtin_nontemporal_load(&rowb[v]);
-          cnt += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+          c += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
         }
-      } else {
-        const u32x4* rowp =
-            reinterpret_cast<const u32x4*>(d.slea + (uint64_t)row * d.row_stride);
-        const uint64_t nvec = d.row_stride / 8;
-        for (; v + 7 * step < nvec; v += 8 * step) {  // eight independent loads in flight
-          u32x4 a[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&rowp[v + u * step]);
-#pragma unroll
-          for (int u = 0; u < 8; ++u) cnt += live8(a[u], lo);
-        }
-        for (; v < nvec; v += step) cnt += live8(__builtin_nontemporal_load(&rowp[v]), lo);
+        add_to(row, c);
       }
-      cnt = wave_sum(cnt);
-      if (lane_id() == 0) red[row][threadIdx.x / kWave] = cnt;
+    } else {
+      // the rows are one flat range: the sweep runs across row ends without draining, and a
+      // lane's counts move to the next row when its index passes a row boundary
+      const u32x4* vec = reinterpret_cast<const u32x4*>(d.slea);
+      const uint64_t nvec = d.row_stride / 8, total = (uint64_t)d.rp * nvec;
+      uint32_t row = (uint32_t)(first / nvec);
+      uint64_t next_b = (uint64_t)(row + 1u) * nvec;  // first vector of the next row
+      uint32_t acc = 0;
+      auto account = [&](uint64_t idx, uint32_t c) {
+        while (idx >= next_b) {
+          add_to(row, acc);
+          acc = 0;
+          ++row;
+          next_b += nvec;
+        }
+        acc += c;
+      };
+      uint64_t v = first;
+      for (; v + 7 * step < total; v += 8 * step) {  // eight independent loads in flight
+        u32x4 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&vec[v + u * step]);
+        if (v + 7 * step < next_b) {  // all eight in the current row
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += live8(a[u], lo);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) account(v + u * step, live8(a[u], lo));
+        }
+      }
+      for (; v < total; v += step) account(v, live8(__builtin_nontemporal_load(&vec[v]), lo));
+      add_to(row, acc);
+    }
+    for (uint32_t j = 0; j < d.rp; ++j) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int jj = 0; jj < kMaxRP; ++jj)
+        if ((uint32_t)jj == j) c = cnt[jj];
+      c = wave_sum(c);
+      if (lane_id() == 0) red[j][threadIdx.x / kWave] = c;
     }
     __syncthreads();
     if (threadIdx.x < d.rp) {
@@ -432,7 +465,7 @@ __device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp,
 // extensions (over u = t ^ top0) are R; every descendant is visited once, depth first:
 // backing up from row i to row i-1 clears row i-1's extension bits from x and recomputes
 // row i-1's extensions above the one just finished.
-__device__ __noinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
+__device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
                                                uint32_t wmask, uint32_t lowmask, uint32_t qmask,
                                                uint32_t x, uint32_t he0, uint32_t i, uint32_t R) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
