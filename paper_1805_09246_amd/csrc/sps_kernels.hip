@@ -222,6 +222,22 @@ __device__ __forceinline__ uint32_t live8(u32x4 v, uint32_t lo) {
   return n;
 }
 
+// Live stamps of 8 cells, two per 32-bit word with packed 16-bit integer operations: the
+// saturating difference stamp - (lo - 1) is nonzero exactly when stamp >= lo, and its
+// minimum with 1 is the 0/1 count of that half.  The result holds the count of the low
+// halves in bits 0-15 and of the high halves in bits 16-31 (each at most 4).
+__device__ __forceinline__ uint32_t live_pairs(uint32_t w, uint32_t lom1, uint32_t ones) {
+  uint32_t d, m;
+  asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(d) : "v"(w), "v"(lom1));
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(d), "v"(ones));
+  return m;
+}
+
+__device__ __forceinline__ uint32_t live8_pairs(u32x4 v, uint32_t lom1, uint32_t ones) {
+  return live_pairs(v.x, lom1, ones) + live_pairs(v.y, lom1, ones) +
+         live_pairs(v.z, lom1, ones) + live_pairs(v.w, lom1, ones);
+}
+
 // Stage 1.  Blocks [0, nb_sle) stream the SLE array as one flat range (grid-stride with eight
 // 16-byte non-temporal loads in flight per lane), so all blocks carry equal work, and add
 // their per-row live-cell counts to row_live (Def. 4).  The
@@ -271,14 +287,17 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
         }
         acc += c;
       };
+      const uint32_t lom1 = (lo - 1u) * 0x10001u, ones = 0x10001u;
       uint64_t v = first;
       for (; v + 7 * step < total; v += 8 * step) {  // eight independent loads in flight
         u32x4 a[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&vec[v + u * step]);
         if (v + 7 * step < next_b) {  // all eight in the current row
+          uint32_t pr = 0;  // packed counts, at most 32 per half
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc += live8(a[u], lo);
+          for (int u = 0; u < 8; ++u) pr += live8_pairs(a[u], lom1, ones);
+          acc += (pr & 0xFFFFu) + (pr >> 16);
         } else {
 #pragma unroll
           for (int u = 0; u < 8; ++u) account(v + u * step, live8(a[u], lo));
