@@ -238,17 +238,55 @@ __device__ __forceinline__ uint32_t live8_pairs(u32x4 v, uint32_t lom1, uint32_t
          live_pairs(v.z, lom1, ones) + live_pairs(v.w, lom1, ones);
 }
 
-// Stage 1.  Blocks [0, nb_sle) stream the SLE array as one flat range (grid-stride with eight
-// 16-byte non-temporal loads in flight per lane), so all blocks carry equal work, and add
-// their per-row live-cell counts to row_live (Def. 4).  The
+// One SRE per lane (64 consecutive SREs per wave): k-weight >= hot cut marks it hot.
+__device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sre_idx) {
+  uint32_t w = 0;
+  if (d.mode == SPS_MODE_DISCRETE) {  // eta bits per SRE: eta / 8 bytes
+    const uint8_t* by = reinterpret_cast<const uint8_t*>(d.sre) + (sre_idx * d.eta >> 3);
+    for (uint32_t b = 0; b < d.eta / 8; ++b) w += __popc((uint32_t)by[b]);
+  } else {
+    const u32x4* cell = reinterpret_cast<const u32x4*>(d.sre + (sre_idx << __builtin_ctz(d.eta)));
+    for (uint32_t v = 0; v < d.eta / 8; ++v) w += live8(cell[v], lo);
+  }
+  const bool hot = w >= d.hot_cut;
+  const uint64_t mask = __ballot(hot);
+  const uint32_t row = (uint32_t)(sre_idx >> d.q);
+  const uint32_t col = (uint32_t)(sre_idx & ((1u << d.q) - 1u));
+  if (lane_id() == 0) {
+    uint32_t* hw = d.hot + (sre_idx >> 5);
+    hw[0] = (uint32_t)mask;
+    hw[1] = (uint32_t)(mask >> 32);
+  }
+  if (hot) {  // the join's layout: all 2^delta extensions of a node in one entry
+    const uint32_t low = col & ((1u << (d.q - d.delta)) - 1u);
+    const uint32_t top = col >> (d.q - d.delta);
+    const uint32_t pos = (row << d.q) + (low << d.delta) + top;
+    atomicOr(&d.hot_t[pos >> 5], 1u << (pos & 31u));
+  }
+  if (row < 2 && mask != 0) {
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(&d.ctrl->hse_count[row], (uint32_t)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (hot) {
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      d.hse[((uint64_t)row << d.q) + base + below] = col;
+    }
+  }
+}
+
+// Stage 1.  All blocks stream the SLE array as one flat range (grid-stride with eight 16-byte
+// non-temporal loads in flight per lane), so all blocks carry equal work, and add their
+// per-row live-cell counts to row_live (Def. 4); then (with_sre) the same waves take the
+// SREs 64 at a time.  The
 // remaining blocks take one SRE per lane: k-weight >= hot cut marks it hot (Sec. 3.3); a
 // wave's 64 verdicts become one ballot word of the hot bitmap, and rows 0 and 1 also append
 // their hot columns to the HSE lists.
-__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t nb_sle) {
+__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t with_sre) {
   __shared__ uint32_t red[kMaxRP][256 / kWave];
   const uint32_t b = blockIdx.x;
-  if (b < nb_sle) {
-    const uint64_t step = (uint64_t)nb_sle * blockDim.x;
+  {
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t first = (uint64_t)b * blockDim.x + threadIdx.x;
     uint32_t cnt[kMaxRP];
 #pragma unroll
@@ -320,44 +358,14 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
       for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
       atomicAdd(&d.ctrl->row_live[threadIdx.x], t);
     }
-    return;
   }
-  const uint64_t sre_idx = (uint64_t)(b - nb_sle) * blockDim.x + threadIdx.x;
-  const uint64_t n_sre = (uint64_t)d.r << d.q;  // multiple of 64 (q >= 6)
-  if (sre_idx - lane_id() >= n_sre) return;     // whole wave out of range
-  uint32_t w = 0;
-  if (d.mode == SPS_MODE_DISCRETE) {  // eta bits per SRE: eta / 8 bytes
-    const uint8_t* by = reinterpret_cast<const uint8_t*>(d.sre) + (sre_idx * d.eta >> 3);
-    for (uint32_t b = 0; b < d.eta / 8; ++b) w += __popc((uint32_t)by[b]);
-  } else {
-    const u32x4* cell = reinterpret_cast<const u32x4*>(d.sre + (sre_idx << __builtin_ctz(d.eta)));
-    for (uint32_t v = 0; v < d.eta / 8; ++v) w += live8(cell[v], lo);
-  }
-  const bool hot = w >= d.hot_cut;
-  const uint64_t mask = __ballot(hot);
-  const uint32_t row = (uint32_t)(sre_idx >> d.q);
-  const uint32_t col = (uint32_t)(sre_idx & ((1u << d.q) - 1u));
-  if (lane_id() == 0) {
-    uint32_t* hw = d.hot + (sre_idx >> 5);
-    hw[0] = (uint32_t)mask;
-    hw[1] = (uint32_t)(mask >> 32);
-  }
-  if (hot) {  // the join's layout: all 2^delta extensions of a node in one entry
-    const uint32_t low = col & ((1u << (d.q - d.delta)) - 1u);
-    const uint32_t top = col >> (d.q - d.delta);
-    const uint32_t pos = (row << d.q) + (low << d.delta) + top;
-    atomicOr(&d.hot_t[pos >> 5], 1u << (pos & 31u));
-  }
-  if (row < 2 && mask != 0) {
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(&d.ctrl->hse_count[row], (uint32_t)__popcll(mask));
-    base = __shfl(base, 0, kWave);
-    if (hot) {
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-          (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      d.hse[((uint64_t)row << d.q) + base + below] = col;
-    }
-  }
+  if (!with_sre) return;
+  // then the SREs, 64 per wave at a time (r 2^q is a multiple of 64: q >= 6)
+  const uint64_t n_groups = ((uint64_t)d.r << d.q) / kWave;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  for (uint64_t g = (uint64_t)b * (blockDim.x / kWave) + wib; g < n_groups; g += n_waves)
+    sre_group(d, lo, g * kWave + lane_id());
 }
 
 // Hot extensions of a node (Alg. 4-5 check, in bulk).  Row i's SRE for the extension t is
@@ -1016,13 +1024,10 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // the SLE array streamed by one block per CU, then one SRE per lane for the hot SREs
-  const uint32_t nb_sle = (uint32_t)n_cu;
-  const uint64_t sre_blocks = (((uint64_t)d.r << d.q) + 255) / 256;
+  // one block per CU: the SLE array streamed, then one SRE per lane for the hot SREs
   {
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)(nb_sle + sre_blocks)), dim3(256), 0, st,
-                       d, lo, nb_sle);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, 1u);
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
@@ -1053,10 +1058,9 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const MlpRef& mlp, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   {
-    // only the SLE-array blocks: the SRE part of the grid is not launched
+    // the SLE array only (with_sre = 0)
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo,
-                       (uint32_t)n_cu);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, 0u);
   }
   if (n) {
     uint32_t blocks = (n + 3) / 4;
