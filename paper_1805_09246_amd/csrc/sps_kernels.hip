@@ -459,19 +459,13 @@ struct HotLists {
 template <bool kSmall>
 __device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp, uint32_t& a,
                                             uint32_t& b) {
-  if (kSmall) {  // p < 2^32
+  if (kSmall) {  // p < 2^32, n0 and n1 < 2^24: the quotient and n1 fit 24-bit factors
     const uint32_t p32 = (uint32_t)p;
-    uint32_t q0 = (uint32_t)((double)p32 * rcp);
-    int32_t rem = (int32_t)(p32 - q0 * n1);
-    if (rem < 0) {
-      --q0;
-      rem += (int32_t)n1;
-    } else if ((uint32_t)rem >= n1) {
-      ++q0;
-      rem -= (int32_t)n1;
-    }
-    a = q0;
-    b = (uint32_t)rem;
+    const uint32_t q0 = (uint32_t)((double)p32 * rcp);
+    const int32_t rem = (int32_t)(p32 - __umul24(q0, n1));
+    const bool neg = rem < 0, over = rem >= (int32_t)n1;
+    a = neg ? q0 - 1u : (over ? q0 + 1u : q0);
+    b = (uint32_t)(neg ? rem + (int32_t)n1 : (over ? rem - (int32_t)n1 : rem));
   } else {
     uint64_t q0 = (uint64_t)((double)p * rcp);
     int64_t rem = (int64_t)(p - q0 * n1);
@@ -532,7 +526,9 @@ __device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* 
   }
 }
 
-template <bool kSmall, typename L>
+// kFullFit: every row's extensions stay below bit 32 ((r-2) delta + q <= 32), so the
+// bit-32 limit never removes an extension and extension bits always shift in range.
+template <bool kSmall, bool kFullFit, typename L>
 __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
                                           u32x2* __restrict__ stk, uint32_t cap, L lists,
                                           uint32_t n0, uint32_t n1) {
@@ -554,7 +550,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
   uint32_t used = 0;  // pairs of the current group already taken (uniform)
   uint32_t size = 0;  // nodes on this wave's stack (uniform)
-  unsigned long long nodes = 0;  // nodes this wave expanded (uniform)
+  uint32_t nodes = 0;  // nodes this wave expanded (uniform; at most a few times 10^5)
   for (;;) {
     const uint32_t popped = size < 64u ? size : 64u;
     const uint32_t need = 64u - popped;
@@ -570,7 +566,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       he0 = nd.y & 0xFFFFFFu;
       i = nd.y >> 24;
     } else if (k < t1 + t2) {
-      const uint64_t pidx = k < t1 ? g_first + used + k : g_first + stride + (k - t1);
+      const uint64_t pidx = g_first + (k < t1 ? used + k : stride + (k - t1));
       uint32_t a, b;
       pair_coords<kSmall>(pidx, n1, rcp, a, b);
       he0 = lists.he0(a);
@@ -580,7 +576,8 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     const uint32_t sx = __umul24(i - 2u, dl) + q;  // first bit of the extension
     if (lane < popped + t1 + t2) {
       const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
-      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sx, dl, wmask, top0);
+      R = hot_tops(tb, q, dl, wmask, i, low);
+      if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
     }
     used += t1;
     if (used == cur_n && nxt_n != 0u) {  // move on to the next group
@@ -594,7 +591,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       while (R) {
         const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
-        const uint32_t addr = sx < 32u ? x | (t << sx) : x;
+        const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
         if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
           const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
           if (pos < d.cand_cap) d.cand[pos] = addr;
@@ -616,17 +613,17 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       while (R) {
         const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
-        const u32x2 child = {sx < 32u ? x | (t << sx) : x, meta};
+        const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
         stk[--pos] = child;
       }
       size = base + total;
     } else {  // no room: every lane searches its own node's subtree depth first instead
       const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
-      nodes += wave_sum(e);
+      nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
       size = base;
     }
   }
-  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, nodes);
+  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
 }
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
@@ -649,24 +646,28 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
-  const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull;
+  // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
+  const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull && n0 < (1u << 24) && n1 < (1u << 24);
+  const bool full = (r - 2u) * d.delta + q <= 32u;
+  auto run = [&](auto lists) {
+    if (small && full)
+      join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);
+    else if (small)
+      join_wave<true, false>(d, tb, stk, cap, lists, n0, n1);
+    else if (full)
+      join_wave<false, true>(d, tb, stk, cap, lists, n0, n1);
+    else
+      join_wave<false, false>(d, tb, stk, cap, lists, n0, n1);
+  };
   if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
     uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
     for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
     for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
     __syncthreads();
-    const HotLists<uint16_t> L{h, h + n0};
-    if (small)
-      join_wave<true>(d, tb, stk, cap, L, n0, n1);
-    else
-      join_wave<false>(d, tb, stk, cap, L, n0, n1);
+    run(HotLists<uint16_t>{h, h + n0});
   } else {
     __syncthreads();
-    const HotLists<uint32_t> L{g0, g1};
-    if (small)
-      join_wave<true>(d, tb, stk, cap, L, n0, n1);
-    else
-      join_wave<false>(d, tb, stk, cap, L, n0, n1);
+    run(HotLists<uint32_t>{g0, g1});
   }
 }
 
