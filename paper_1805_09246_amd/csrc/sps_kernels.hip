@@ -326,20 +326,38 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
         acc += c;
       };
       const uint32_t lom1 = (lo - 1u) * 0x10001u, ones = 0x10001u;
-      uint64_t v = first;
-      for (; v + 7 * step < total; v += 8 * step) {  // eight independent loads in flight
-        u32x4 a[8];
+      // two batches of eight loads, the next issued before the current one is counted; load
+      // indices are clamped into the array so the batches are unconditional
+      auto load8 = [&](u32x4* a, uint64_t v0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(&vec[v + u * step]);
-        if (v + 7 * step < next_b) {  // all eight in the current row
+        for (int u = 0; u < 8; ++u) {
+          const uint64_t j = v0 + u * step;
+          a[u] = __builtin_nontemporal_load(&vec[j < total ? j : total - 1]);
+        }
+      };
+      auto count8 = [&](const u32x4* a, uint64_t v0) {
+        if (v0 + 7 * step < next_b) {  // all eight in the current row
           uint32_t pr = 0;  // packed counts, at most 32 per half
 #pragma unroll
           for (int u = 0; u < 8; ++u) pr += live8_pairs(a[u], lom1, ones);
           acc += (pr & 0xFFFFu) + (pr >> 16);
         } else {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) account(v + u * step, live8(a[u], lo));
+          for (int u = 0; u < 8; ++u) account(v0 + u * step, live8(a[u], lo));
         }
+      };
+      uint64_t v = first;
+      u32x4 A[8], B[8];
+      load8(A, v);
+      for (;;) {
+        if (v + 7 * step >= total) break;
+        load8(B, v + 8 * step);
+        count8(A, v);
+        v += 8 * step;
+        if (v + 7 * step >= total) break;
+        load8(A, v + 8 * step);
+        count8(B, v);
+        v += 8 * step;
       }
       for (; v < total; v += step) account(v, live8(__builtin_nontemporal_load(&vec[v]), lo));
       add_to(row, acc);
