@@ -23,6 +23,20 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP moves: shifts of 1, 2, 4 and 8 lanes within
+// each 16-lane row, then the last lane of row 0 (and of row 2) added to row 1 (and 3), then
+// the last lane of row 1 added to rows 2 and 3.  Lanes whose source is outside the row keep
+// the `old` operand, 0.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
 // ---------------------------------------------------------------------------------------
 // Ingest.  One lane per IP pair: H3(bip) picks the SLE cell, LH_i(aip) the SLE of row i
 // (Alg. 6); when LSB(H1(bip)) >= tau (low tau bits of H1 clear), H2(bip) picks the SRE
@@ -554,7 +568,6 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   const uint64_t pairs = (uint64_t)n0 * n1;
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
-  const uint32_t cbits = dl + 1u;  // a node has at most 2^delta children
   const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
   const double rcp = 1.0 / (double)n1;
 
@@ -566,6 +579,16 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     return first < pairs ? (pairs - first < 64ull ? (uint32_t)(pairs - first) : 64u) : 0u;
   };
   uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
+  // (a, b) of the first pair of the current and of the next group (uniform); with n1 >= 128 a
+  // lane's pair is at most 126 further on, one step past the end of row a at most
+  const bool near = n1 >= 128u;
+  const uint32_t step_a = (uint32_t)(stride / n1), step_b = (uint32_t)(stride % n1);
+  uint32_t ca = (uint32_t)(g_first / n1), cb = (uint32_t)(g_first % n1);
+  uint32_t na = ca + step_a, nb = cb + step_b;
+  if (nb >= n1) {
+    nb -= n1;
+    ++na;
+  }
   uint32_t used = 0;  // pairs of the current group already taken (uniform)
   uint32_t size = 0;  // nodes on this wave's stack (uniform)
   uint32_t nodes = 0;  // nodes this wave expanded (uniform; at most a few times 10^5)
@@ -584,9 +607,17 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       he0 = nd.y & 0xFFFFFFu;
       i = nd.y >> 24;
     } else if (k < t1 + t2) {
-      const uint64_t pidx = g_first + (k < t1 ? used + k : stride + (k - t1));
       uint32_t a, b;
-      pair_coords<kSmall>(pidx, n1, rcp, a, b);
+      if (near) {
+        a = k < t1 ? ca : na;
+        b = k < t1 ? cb + used + k : nb + (k - t1);
+        if (b >= n1) {
+          b -= n1;
+          ++a;
+        }
+      } else {
+        pair_coords<kSmall>(g_first + (k < t1 ? used + k : stride + (k - t1)), n1, rcp, a, b);
+      }
       he0 = lists.he0(a);
       x = he0 ^ lists.he1(b);
     }
@@ -603,6 +634,14 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       cur_n = nxt_n;
       nxt_n = group_n(g_first + stride);
       used = t2;
+      ca = na;
+      cb = nb;
+      na += step_a;
+      nb += step_b;
+      if (nb >= n1) {
+        nb -= n1;
+        ++na;
+      }
     }
     const bool last = i + 1u == r;
     if (last) {
@@ -617,13 +656,9 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       }
     }
     const uint32_t c = popc32(R);  // children to push (0 at the last row)
-    uint32_t below = 0, total = 0;
-    for (uint32_t bit = 0; bit < cbits; ++bit) {
-      const uint64_t m = __ballot((c >> bit) & 1u);
-      below += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << bit;
-      total += (uint32_t)__popcll(m) << bit;
-    }
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+    const uint32_t below = incl - c;
     const uint32_t base = size - popped;
     if (base + total <= cap) {  // uniform: the children fit on the stack
       uint32_t pos = base + total - below;  // this lane's children end here
@@ -632,7 +667,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
         const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
         const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
-        stk[--pos] = child;
+        if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
       }
       size = base + total;
     } else {  // no room: every lane searches its own node's subtree depth first instead
