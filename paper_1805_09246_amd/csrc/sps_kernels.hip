@@ -474,7 +474,7 @@ __host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
 // what the stack usually holds.
 uint32_t join_stack_entries(uint32_t dl) {
   const uint32_t need = 64u * (1u << dl) + 64u;
-  return need > 768u ? need : 768u;
+  return need > 512u ? need : 512u;
 }
 
 // Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (global).
@@ -724,9 +724,9 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   }
 }
 
-// Launch shape of the join: as many waves per block as the LDS allows (up to 16) after the
-// hot table (when it is small) and a reserve for the hot lists; one block per compute
-// unit.
+// Launch shape of the join: one or two blocks per compute unit, whichever holds more waves
+// (up to 16 per block) after each block's copy of the hot table (when it is small) and a
+// reserve for the hot lists; the lists take whatever LDS is left.
 struct JoinShape {
   bool tb_lds;
   uint32_t cap, waves, lds, blocks, list_words;
@@ -740,12 +740,25 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
   const uint32_t fixed = s.tb_lds ? tb : 0u;
-  s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
-  if (s.waves > kJoinWaves) s.waves = kJoinWaves;
-  if (s.waves < 1u) s.waves = 1u;
-  s.list_words = (kLdsBytes - fixed - s.waves * stack) / 4u;
-  s.lds = kLdsBytes;
-  s.blocks = (uint32_t)n_cu;
+  uint32_t best_total = 0;
+  for (uint32_t per_cu = 1; per_cu <= 2; ++per_cu) {
+    const uint32_t lds = kLdsBytes / per_cu;
+    if (lds < fixed + stack + reserve) continue;
+    uint32_t w = (lds - fixed - reserve) / stack;
+    if (w > kJoinWaves) w = kJoinWaves;
+    if (w * per_cu > best_total) {
+      best_total = w * per_cu;
+      s.waves = w;
+      s.lds = lds;
+      s.blocks = (uint32_t)n_cu * per_cu;
+    }
+  }
+  if (best_total == 0) {  // not reached under the parameter limits (stack <= 16.5 KiB)
+    s.waves = 1;
+    s.lds = kLdsBytes;
+    s.blocks = (uint32_t)n_cu;
+  }
+  s.list_words = (s.lds - fixed - s.waves * stack) / 4u;
   return s;
 }
 
