@@ -80,23 +80,39 @@ __device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__
   }
 }
 
+// XCD-aware ingest.  A host's recorders are written from one XCD only, so the repeated
+// writes of a heavy host merge in that XCD's L2 instead of being spread over eight L2s that
+// each write the same lines back.  Consecutive workgroups go to consecutive XCDs, so the grid
+// is cut into groups of n_cls consecutive blocks; every block of a group reads the same
+// packets and keeps those whose host class (top bits of a multiplicative hash of aip) is its
+// position in the group.  The stores are the same plain stamp stores in any order.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t host_class(uint32_t aip) { return (aip * 0x9E3779B1u) >> 29; }
+
 __global__ void __launch_bounds__(256) k_ingest(Dev d, const u32x2* __restrict__ pkts,
-                                                uint64_t n, uint16_t stamp) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const u32x2 pk = __builtin_nontemporal_load(&pkts[i]);
-    ingest_pair(d, d.sre, d.slea, pk.x, pk.y, stamp);
+                                                uint64_t n, uint16_t stamp, uint32_t n_cls) {
+  const uint32_t cls = blockIdx.x % n_cls, cls_mask = n_cls - 1u;
+  const uint64_t stride = (uint64_t)(gridDim.x / n_cls) * blockDim.x;
+  for (uint64_t i = (uint64_t)(blockIdx.x / n_cls) * blockDim.x + threadIdx.x; i < n;
+       i += stride) {
+    const u32x2 pk = pkts[i];
+    const uint32_t aip = d.anet_side ? pk.x : pk.y;
+    if ((host_class(aip) & cls_mask) == cls) ingest_pair(d, d.sre, d.slea, pk.x, pk.y, stamp);
   }
 }
 
 hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
                          int blocks, int threads, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  uint64_t need = (n + threads - 1) / threads;
-  if ((uint64_t)blocks > need) blocks = (int)need;
+  const uint64_t need = (n + threads - 1) / threads;
+  uint32_t n_cls = blocks >= (int)kXcds ? kXcds : 1u;
+  uint64_t b = (uint64_t)blocks / n_cls * n_cls;
+  if (b > need * n_cls) b = need * n_cls;
+  if (b < n_cls) b = n_cls;
   ProfScope ps(SPS_STAGE_INGEST, st);
-  hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(threads), 0, st, d,
-                     reinterpret_cast<const u32x2*>(pkts), n, stamp);
+  hipLaunchKernelGGL(k_ingest, dim3((uint32_t)b), dim3(threads), 0, st, d,
+                     reinterpret_cast<const u32x2*>(pkts), n, stamp, n_cls);
   return hipGetLastError();
 }
 
@@ -474,7 +490,7 @@ __host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
 // what the stack usually holds.
 uint32_t join_stack_entries(uint32_t dl) {
   const uint32_t need = 64u * (1u << dl) + 64u;
-  return need > 512u ? need : 512u;
+  return need > 768u ? need : 768u;
 }
 
 // Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (global).
@@ -724,9 +740,10 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   }
 }
 
-// Launch shape of the join: one or two blocks per compute unit, whichever holds more waves
-// (up to 16 per block) after each block's copy of the hot table (when it is small) and a
-// reserve for the hot lists; the lists take whatever LDS is left.
+// Launch shape of the join: one block per compute unit with as many waves (up to 16) as the
+// LDS holds after the hot table (when it is small) and a reserve for the hot lists; the lists
+// take whatever LDS is left.  (Two blocks of 10 waves per CU, with smaller stacks, measured
+// 7 % slower at the config-2 shape than one block of 16.)
 struct JoinShape {
   bool tb_lds;
   uint32_t cap, waves, lds, blocks, list_words;
@@ -741,7 +758,7 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
   const uint32_t fixed = s.tb_lds ? tb : 0u;
   uint32_t best_total = 0;
-  for (uint32_t per_cu = 1; per_cu <= 2; ++per_cu) {
+  for (uint32_t per_cu = 1; per_cu <= 1; ++per_cu) {  // two blocks per CU measured slower
     const uint32_t lds = kLdsBytes / per_cu;
     if (lds < fixed + stack + reserve) continue;
     uint32_t w = (lds - fixed - reserve) / stack;
