@@ -757,24 +757,11 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
   const uint32_t fixed = s.tb_lds ? tb : 0u;
-  uint32_t best_total = 0;
-  for (uint32_t per_cu = 1; per_cu <= 1; ++per_cu) {  // two blocks per CU measured slower
-    const uint32_t lds = kLdsBytes / per_cu;
-    if (lds < fixed + stack + reserve) continue;
-    uint32_t w = (lds - fixed - reserve) / stack;
-    if (w > kJoinWaves) w = kJoinWaves;
-    if (w * per_cu > best_total) {
-      best_total = w * per_cu;
-      s.waves = w;
-      s.lds = lds;
-      s.blocks = (uint32_t)n_cu * per_cu;
-    }
-  }
-  if (best_total == 0) {  // not reached under the parameter limits (stack <= 16.5 KiB)
-    s.waves = 1;
-    s.lds = kLdsBytes;
-    s.blocks = (uint32_t)n_cu;
-  }
+  s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
+  if (s.waves > kJoinWaves) s.waves = kJoinWaves;
+  if (s.waves < 1u) s.waves = 1u;
+  s.lds = kLdsBytes;
+  s.blocks = (uint32_t)n_cu;
   s.list_words = (s.lds - fixed - s.waves * stack) / 4u;
   return s;
 }
