@@ -117,13 +117,16 @@ hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t
 }
 
 // Batched ingest: the packets of m routers (same shape and hashes, separate arrays) are cut
-// into tiles; work items are tiles, so one launch covers uneven batches.  Block b takes
-// tiles b, b + gridDim.x, ...; the router of a tile is found by binary search of the tile
+// into tiles; work items are tiles, so one launch covers uneven batches.  Block group g takes
+// tiles g, g + groups, ...; the router of a tile is found by binary search of the tile
 // prefix sums held in the kernel arguments.
 __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uint32_t m,
-                                                        uint32_t tile, uint16_t stamp) {
+                                                        uint32_t tile, uint16_t stamp,
+                                                        uint32_t n_cls) {
+  // tiles go to groups of n_cls consecutive blocks, one host class per block (see k_ingest)
+  const uint32_t cls = blockIdx.x % n_cls, cls_mask = n_cls - 1u;
   const uint64_t total = t.tile_start[m];
-  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  for (uint64_t w = blockIdx.x / n_cls; w < total; w += gridDim.x / n_cls) {
     uint32_t lo = 0, hi = m;  // find j with tile_start[j] <= w < tile_start[j+1]
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
@@ -135,8 +138,9 @@ __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uin
     if (last > it.n) last = it.n;
     const u32x2* pk2 = reinterpret_cast<const u32x2*>(it.pkts);
     for (uint64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
-      const u32x2 pk = __builtin_nontemporal_load(&pk2[i]);
-      ingest_pair(d, it.sre, it.slea, pk.x, pk.y, stamp);
+      const u32x2 pk = pk2[i];
+      const uint32_t aip = d.anet_side ? pk.x : pk.y;
+      if ((host_class(aip) & cls_mask) == cls) ingest_pair(d, it.sre, it.slea, pk.x, pk.y, stamp);
     }
   }
 }
@@ -146,10 +150,13 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
                                  hipStream_t st) {
   const uint64_t total = t.tile_start[m];
   if (total == 0) return hipSuccess;
-  if ((uint64_t)blocks > total) blocks = (int)total;
+  const uint32_t n_cls = blocks >= (int)kXcds ? kXcds : 1u;
+  uint64_t b = (uint64_t)blocks / n_cls * n_cls;
+  if (b > total * n_cls) b = total * n_cls;
+  if (b < n_cls) b = n_cls;
   ProfScope ps(SPS_STAGE_INGEST_BATCHED, st);
-  hipLaunchKernelGGL(k_ingest_batched, dim3(blocks), dim3(threads), 0, st, shape, t, m, tile,
-                     stamp);
+  hipLaunchKernelGGL(k_ingest_batched, dim3((uint32_t)b), dim3(threads), 0, st, shape, t, m,
+                     tile, stamp, n_cls);
   return hipGetLastError();
 }
 
