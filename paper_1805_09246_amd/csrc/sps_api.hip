@@ -105,7 +105,7 @@ uint64_t splitmix64_next(uint64_t& st) {
 }
 
 struct Layout {
-  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, pend, kept, sorted, total;
+  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, total;
   uint64_t row_len, row_stride, sre_bytes, slea_bytes;
 };
 
@@ -133,7 +133,6 @@ Layout layout_of(const sps_params* p) {
   L.hot_t = o;  o += round_up(((uint64_t)p->r << p->q) / 8, 256);
   L.hse = o;    o += round_up(((uint64_t)2 << p->q) * 4, 256);
   L.cand = o;   o += round_up(cap * 4, 256);
-  L.pend = o;   o += round_up(cap * 4, 256);
   L.kept = o;   o += round_up(cap * sizeof(sps_result), 256);
   L.sorted = o; o += round_up(cap * sizeof(sps_result), 256);
   L.total = o;
@@ -318,7 +317,6 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.hot_t = reinterpret_cast<uint32_t*>(b + L.hot_t);
   d.hse = reinterpret_cast<uint32_t*>(b + L.hse);
   d.cand = reinterpret_cast<uint32_t*>(b + L.cand);
-  d.pend = reinterpret_cast<uint32_t*>(b + L.pend);
   d.kept = reinterpret_cast<sps_result*>(b + L.kept);
   s->d_info = reinterpret_cast<uint32_t*>(b + L.info);
   s->d_sorted = reinterpret_cast<sps_result*>(b + L.sorted);

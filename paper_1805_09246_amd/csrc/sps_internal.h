@@ -22,8 +22,7 @@ struct Ctrl {
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
   uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
   unsigned long long join_nodes;  // nodes the candidate search expanded
-  uint32_t n_pend;            // candidates left for the sort kernel to estimate (see k_join)
-  uint32_t pad0;
+  uint32_t pad0[2];
   // copies of the last scan's counters, for inspection (not cleared)
   uint32_t last_row_live[kMaxRP];
   uint32_t last_n_cand;
@@ -51,7 +50,6 @@ struct Dev {
                           // (low << delta) + top of row i is hot_i[low | top << (q - delta)]
   uint32_t* hse;          // [2][2^q] hot-SRE column lists of rows 0 and 1
   uint32_t* cand;         // [cand_cap] recovered candidates
-  uint32_t* pend;         // [cand_cap] candidates the join found without estimating them
   sps_result* kept;       // [cand_cap] kept hosts, unordered
   Ctrl* ctrl;
   uint64_t row_len;       // L' = 2^q' delta' + eta' - delta'

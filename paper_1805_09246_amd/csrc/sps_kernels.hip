@@ -423,6 +423,364 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
     sre_group(d, lo, g * kWave + lane_id());
 }
 
+// Hot extensions of a node (Alg. 4-5 check, in bulk).  Row i's SRE for the extension t is
+// he0 ^ B(i): its low q-delta bits are `low` (B(i)'s low bits xor he0's, from bits already
+// fixed) and its top delta bits are u = t ^ top0 (top0: he0's top bits).  The transposed
+// table keeps, for each (row, low), the 2^delta hot bits over u in one entry; the result is
+// that entry, indexed by u (the caller maps u back to t = u ^ top0).
+__device__ __forceinline__ uint32_t hot_tops(const uint32_t* __restrict__ tb, uint32_t q,
+                                             uint32_t dl, uint32_t wmask, uint32_t row,
+                                             uint32_t low) {
+  const uint32_t pos = (row << q) + (low << dl);
+  return (tb[pos >> 5] >> (pos & 31u)) & wmask;
+}
+
+// The extensions allowed by bit 32 (t < 2^f, see fit_mask) as a mask over u = t ^ top0: a
+// block of 2^f consecutive u values starting at top0 with its low f bits cleared.
+__device__ __forceinline__ uint32_t fit_tops(uint32_t sx, uint32_t dl, uint32_t wmask,
+                                             uint32_t top0) {
+  const uint32_t f = sx >= 32u ? 0u : (32u - sx < dl ? 32u - sx : dl);
+  if (f == dl) return wmask;
+  const uint32_t blk = 1u << f;  // <= 16 here
+  return ((1u << blk) - 1u) << (top0 & ~(blk - 1u));
+}
+
+// Extensions t of row i whose bits stay below bit 32 (bit positions [(i-2)delta + q, ...)).
+__host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i) {
+  const uint32_t sh = (i - 2u) * dl + q;
+  const uint32_t width = 1u << dl;
+  if (sh >= 32u) return 1u;
+  const uint32_t free_bits = 32u - sh;
+  if (free_bits >= dl) return width == 32u ? 0xFFFFFFFFu : ((1u << width) - 1u);
+  return (1u << (1u << free_bits)) - 1u;
+}
+
+// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  A pair (he0, he1) of hot SREs of
+// rows 0 and 1 fixes B(1) = he0 ^ he1, the address bits [0, q).  Row i >= 2 adds the delta
+// bits [(i-2)delta + q, (i-1)delta + q); the overlap of B(i) with B(i-1) holds by
+// construction, so an extension survives when SRE he0 ^ B(i) of row i is hot and no bit at
+// or above 32 is set.  Each node's surviving extensions come from one load of the
+// transposed hot table.  A full tuple is kept when RHFG[0] of the address is he0.
+//
+// Work: every wave runs its own search with a stack of nodes in LDS.  A node is
+// (x, he0, i): the address bits fixed so far, the row-0 SRE and the next row to extend.
+// Each iteration the wave takes up to 64 nodes from the top of its stack, tops the batch
+// up with fresh (he0, he1) pairs when the stack holds fewer than 64, expands all of them at
+// once (one node per lane) and pushes the children; nodes at the last row check their
+// extensions in place.  Children of lanes nearer the top are pushed above the others, so
+// the stack stays ordered by row from bottom to top and stays small: a batch that reaches
+// into the nodes of row i takes every node above row i with it, so no row holds more than
+// 64 times the extensions of one node.  That bound (64 * sum_i |extensions of row i|, 2048
+// entries at q = 14, delta = 2) would cost so much LDS that few waves fit on a compute unit,
+// so the stack is smaller (join_stack_entries); when a batch's children do not fit, each
+// lane instead searches its own node's subtree depth first in registers (join_lane_dfs)
+// and nothing is pushed.  Either way every node is expanded exactly once.
+//
+// Pairs are numbered a * n1 + b and cut into groups of 64; wave w of W takes groups w,
+// w + W, w + 2W, ... in order (no shared counter).  Lane j keeps the (a, b) of slot j of the
+// wave's current group; a lane taking a pair reads its coordinates from the owning slot
+// (one cross-lane move), and the next group's are the same advanced by 64 W pairs.  The
+// hot table, the stacks and (when they fit) the two hot lists live in LDS, so the loop
+// touches no global memory except to record a candidate.
+constexpr uint32_t kLdsBytes = 160u << 10;  // LDS of one gfx950 compute unit
+constexpr uint32_t kJoinWaves = 16;        // waves per block at most
+
+__host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __popc(v);
+#else
+  return (uint32_t)__builtin_popcount(v);
+#endif
+}
+
+// Stack entries per wave: room for a full batch of children (64 nodes x 2^delta) on top of
+// what the stack usually holds.
+uint32_t join_stack_entries(uint32_t dl) {
+  const uint32_t need = 64u * (1u << dl) + 64u;
+  return need > 768u ? need : 768u;
+}
+
+// Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (global).
+template <typename T>
+struct HotLists {
+  const T* l0;
+  const T* l1;
+  __device__ __forceinline__ uint32_t he0(uint32_t a) const { return l0[a]; }
+  __device__ __forceinline__ uint32_t he1(uint32_t b) const { return l1[b]; }
+};
+
+// a = p / n1, b = p % n1 from a double-precision estimate corrected by one step (the
+// estimate is off by less than one: p < 2^48 and rcp = 1/n1 to 53 bits).
+template <bool kSmall>
+__device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp, uint32_t& a,
+                                            uint32_t& b) {
+  if (kSmall) {  // p < 2^32, n0 and n1 < 2^24: the quotient and n1 fit 24-bit factors
+    const uint32_t p32 = (uint32_t)p;
+    const uint32_t q0 = (uint32_t)((double)p32 * rcp);
+    const int32_t rem = (int32_t)(p32 - __umul24(q0, n1));
+    const bool neg = rem < 0, over = rem >= (int32_t)n1;
+    a = neg ? q0 - 1u : (over ? q0 + 1u : q0);
+    b = (uint32_t)(neg ? rem + (int32_t)n1 : (over ? rem - (int32_t)n1 : rem));
+  } else {
+    uint64_t q0 = (uint64_t)((double)p * rcp);
+    int64_t rem = (int64_t)(p - q0 * n1);
+    if (rem < 0) {
+      --q0;
+      rem += n1;
+    } else if ((uint64_t)rem >= n1) {
+      ++q0;
+      rem -= n1;
+    }
+    a = (uint32_t)q0;
+    b = (uint32_t)rem;
+  }
+}
+
+// Subtree search of one lane, with the partial address as its only state: used when a
+// wave's stack has no room for a batch's children.  (x, he0, i) is a node whose row-i
+// extensions (over u = t ^ top0) are R; every descendant is visited once, depth first:
+// backing up from row i to row i-1 clears row i-1's extension bits from x and recomputes
+// row i-1's extensions above the one just finished.
+__device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
+                                               uint32_t wmask, uint32_t lowmask, uint32_t qmask,
+                                               uint32_t x, uint32_t he0, uint32_t i, uint32_t R) {
+  const uint32_t q = d.q, dl = d.delta, r = d.r;
+  const uint32_t top0 = he0 >> (q - dl), dmask = (1u << dl) - 1u;
+  const uint32_t i0 = i;
+  uint32_t expanded = 0;  // nodes expanded below (x, he0, i)
+  for (;;) {
+    if (R == 0u) {
+      if (i == i0) return expanded;
+      --i;  // back up: the extension taken at row i
+      const uint32_t sx = (i - 2u) * dl + q;
+      const uint32_t t = sx < 32u ? (x >> sx) & dmask : 0u;
+      if (sx < 32u) x &= (1u << sx) - 1u;
+      const uint32_t u = t ^ top0;
+      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
+      const uint32_t above = u >= 31u ? 0u : ~((2u << u) - 1u);
+      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sx, dl, wmask, top0) & above;
+      continue;
+    }
+    const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+    R &= R - 1u;
+    const uint32_t sx = (i - 2u) * dl + q;
+    const uint32_t xi = sx < 32u ? x | (t << sx) : x;
+    if (i + 1u == r) {
+      if ((fmix32(xi ^ d.seed_rhfg0) & qmask) == he0) {
+        const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+        if (pos < d.cand_cap) d.cand[pos] = xi;
+      }
+    } else {
+      x = xi;
+      ++i;
+      ++expanded;
+      const uint32_t sxn = (i - 2u) * dl + q;
+      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
+      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sxn, dl, wmask, top0);
+    }
+  }
+}
+
+// kFullFit: every row's extensions stay below bit 32 ((r-2) delta + q <= 32), so the
+// bit-32 limit never removes an extension and extension bits always shift in range.
+template <bool kSmall, bool kFullFit, typename L>
+__device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
+                                          u32x2* __restrict__ stk, uint32_t cap, L lists,
+                                          uint32_t n0, uint32_t n1) {
+  const uint32_t q = d.q, dl = d.delta, r = d.r;
+  const uint64_t pairs = (uint64_t)n0 * n1;
+  const uint32_t lane = lane_id();
+  const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
+  const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
+  const double rcp = 1.0 / (double)n1;
+
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
+  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  const uint64_t stride = 64ull * n_waves;  // pairs between a wave's groups
+  uint64_t g_first = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + wib) * 64ull;
+  auto group_n = [pairs](uint64_t first) -> uint32_t {
+    return first < pairs ? (pairs - first < 64ull ? (uint32_t)(pairs - first) : 64u) : 0u;
+  };
+  uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
+  // (a, b) of the first pair of the current and of the next group (uniform); with n1 >= 128 a
+  // lane's pair is at most 126 further on, one step past the end of row a at most
+  const bool near = n1 >= 128u;
+  const uint32_t step_a = (uint32_t)(stride / n1), step_b = (uint32_t)(stride % n1);
+  uint32_t ca = (uint32_t)(g_first / n1), cb = (uint32_t)(g_first % n1);
+  uint32_t na = ca + step_a, nb = cb + step_b;
+  if (nb >= n1) {
+    nb -= n1;
+    ++na;
+  }
+  uint32_t used = 0;  // pairs of the current group already taken (uniform)
+  uint32_t size = 0;  // nodes on this wave's stack (uniform)
+  uint32_t nodes = 0;  // nodes this wave expanded (uniform; at most a few times 10^5)
+  for (;;) {
+    const uint32_t popped = size < 64u ? size : 64u;
+    const uint32_t need = 64u - popped;
+    const uint32_t t1 = cur_n - used < need ? cur_n - used : need;  // from the current group
+    const uint32_t t2 = nxt_n < need - t1 ? nxt_n : need - t1;      // then from the next
+    if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
+    nodes += popped + t1 + t2;
+    const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
+    uint32_t x = 0, he0 = 0, i = 2, R = 0;
+    if (lane < popped) {
+      const u32x2 nd = stk[size - 1u - lane];
+      x = nd.x;
+      he0 = nd.y & 0xFFFFFFu;
+      i = nd.y >> 24;
+    } else if (k < t1 + t2) {
+      uint32_t a, b;
+      if (near) {
+        a = k < t1 ? ca : na;
+        b = k < t1 ? cb + used + k : nb + (k - t1);
+        if (b >= n1) {
+          b -= n1;
+          ++a;
+        }
+      } else {
+        pair_coords<kSmall>(g_first + (k < t1 ? used + k : stride + (k - t1)), n1, rcp, a, b);
+      }
+      he0 = lists.he0(a);
+      x = he0 ^ lists.he1(b);
+    }
+    const uint32_t top0 = he0 >> (q - dl);
+    const uint32_t sx = __umul24(i - 2u, dl) + q;  // first bit of the extension
+    if (lane < popped + t1 + t2) {
+      const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
+      R = hot_tops(tb, q, dl, wmask, i, low);
+      if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
+    }
+    used += t1;
+    if (used == cur_n && nxt_n != 0u) {  // move on to the next group
+      g_first += stride;
+      cur_n = nxt_n;
+      nxt_n = group_n(g_first + stride);
+      used = t2;
+      ca = na;
+      cb = nb;
+      na += step_a;
+      nb += step_b;
+      if (nb >= n1) {
+        nb -= n1;
+        ++na;
+      }
+    }
+    const bool last = i + 1u == r;
+    if (last) {
+      while (R) {
+        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+        R &= R - 1u;
+        const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
+        if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+          const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+          if (pos < d.cand_cap) d.cand[pos] = addr;
+        }
+      }
+    }
+    const uint32_t c = popc32(R);  // children to push (0 at the last row)
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+    const uint32_t below = incl - c;
+    const uint32_t base = size - popped;
+    if (base + total <= cap) {  // uniform: the children fit on the stack
+      uint32_t pos = base + total - below;  // this lane's children end here
+      const uint32_t meta = he0 | ((i + 1u) << 24);
+      while (R) {
+        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+        R &= R - 1u;
+        const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
+        if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
+      }
+      size = base + total;
+    } else {  // no room: every lane searches its own node's subtree depth first instead
+      const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+      nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
+      size = base;
+    }
+  }
+  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
+}
+
+// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
+template <bool kTbLds>
+__global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
+                                                          uint32_t list_words) {
+  extern __shared__ uint32_t sh[];
+  const uint32_t q = d.q, r = d.r;
+  const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
+  if (n0 == 0u || n1 == 0u) return;
+  const uint32_t* __restrict__ tb = d.hot_t;
+  uint32_t off = 0;
+  if (kTbLds) {
+    const uint32_t words = (r << q) >> 5;
+    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
+    tb = sh;
+    off = words;  // even: q >= 6
+  }
+  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
+  uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
+  const uint32_t* g0 = d.hse;
+  const uint32_t* g1 = d.hse + (1u << q);
+  // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
+  const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull && n0 < (1u << 24) && n1 < (1u << 24);
+  const bool full = (r - 2u) * d.delta + q <= 32u;
+  auto run = [&](auto lists) {
+    if (small && full)
+      join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);
+    else if (small)
+      join_wave<true, false>(d, tb, stk, cap, lists, n0, n1);
+    else if (full)
+      join_wave<false, true>(d, tb, stk, cap, lists, n0, n1);
+    else
+      join_wave<false, false>(d, tb, stk, cap, lists, n0, n1);
+  };
+  if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
+    uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
+    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
+    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
+    __syncthreads();
+    run(HotLists<uint16_t>{h, h + n0});
+  } else {
+    __syncthreads();
+    run(HotLists<uint32_t>{g0, g1});
+  }
+}
+
+// Launch shape of the join: one block per compute unit with as many waves (up to 16) as the
+// LDS holds after the hot table (when it is small) and a reserve for the hot lists; the lists
+// take whatever LDS is left.  (Two blocks of 10 waves per CU, with smaller stacks, measured
+// 7 % slower at the config-2 shape than one block of 16.)
+struct JoinShape {
+  bool tb_lds;
+  uint32_t cap, waves, lds, blocks, list_words;
+};
+
+JoinShape join_shape(const Dev& d, int n_cu) {
+  JoinShape s{};
+  s.cap = join_stack_entries(d.delta);
+  const uint32_t stack = s.cap * 8u;  // at most 16.5 KiB
+  const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
+  const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
+  s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
+  const uint32_t fixed = s.tb_lds ? tb : 0u;
+  s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
+  if (s.waves > kJoinWaves) s.waves = kJoinWaves;
+  if (s.waves < 1u) s.waves = 1u;
+  s.lds = kLdsBytes;
+  s.blocks = (uint32_t)n_cu;
+  s.list_words = (s.lds - fixed - s.waves * stack) / 4u;
+  return s;
+}
+
+hipError_t prepare_join() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+}
+
 // Union SLE of host x (Alg. 8): cell z keeps the smallest stamp over the r' rows, i.e. the
 // largest distance, so it is live only when live in every row.  When SLEs start on 8-cell
 // boundaries each lane takes 8 consecutive cells per pass (one 16-byte load per row, all
@@ -558,455 +916,6 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
-// Product of the row setting factors SF(i, k) of Def. 4 (rows in order), from the row live
-// counts of the current scan.
-__device__ __forceinline__ double row_factor_product(const Dev& d) {
-  double P = 1.0;
-  for (uint32_t i = 0; i < d.rp; ++i)
-    P = P * ((double)d.ctrl->row_live[i] / (double)d.row_len);
-  return P;
-}
-
-// Stage 3 for one host x (wave-uniform): union SLE (Alg. 8), corrected weight (Eq. 12),
-// linear counting (Eq. 9), the learned estimator when kMlp, and the flags.  Every lane
-// returns the same record.
-template <bool kMlp>
-__device__ __forceinline__ sps_result estimate_host(const Dev& d, uint32_t x, uint32_t cur,
-                                                    uint32_t lo, double threshold, double P,
-                                                    const MlpRef& mlp) {
-  const uint32_t lane = lane_id();
-  uint32_t U, feat;
-  usle_counts(d, x, cur, lo, kMlp ? SPS_MLP_IN : 0u, U, feat);
-  const double etap = (double)d.etap;
-  double w;
-  uint32_t flags = 0;
-  if (P >= 1.0)
-    w = (double)U;
-  else
-    w = ((double)U - etap * P) / (1.0 - P);
-  if (w < 0.0) {
-    w = 0.0;
-    flags |= SPS_F_CLAMPLOW;
-  }
-  if (w > etap - 1.0) {
-    w = etap - 1.0;
-    flags |= SPS_F_SATURATED;
-  }
-  double est = -etap * log1p(-w / etap);
-  if (kMlp) {
-    // the network replaces linear counting only inside its validated domain
-    const float f = lane < SPS_MLP_IN ? (float)feat / (float)d.etap : 0.f;
-    const bool in_range = lane >= SPS_MLP_IN || (f >= mlp.lo[lane] && f <= mlp.hi[lane]);
-    const bool all_in = __ballot(!in_range) == 0;
-    const bool informative = __shfl(feat, 0, kWave) < d.etap - 1u;
-    const float y = mlp_forward_wave(mlp.w, lane < SPS_MLP_IN ? mlp_encode(feat, d.etap) : 0.f);
-    if (U >= mlp.min_live && all_in && informative && y >= 0.f && y <= mlp.log_max) {
-      est = (double)expf(y);
-      flags |= SPS_F_MLP;
-    } else {
-      flags |= SPS_F_LC_FALLBACK;
-    }
-  }
-  if (fabs(est - threshold) <= 1e-9 * threshold) flags |= SPS_F_NEAR;
-  sps_result res;
-  res.host = x;
-  res.live = U;
-  res.flags = flags;
-  res.pad = 0;
-  res.estimate = est;
-  return res;
-}
-
-// Final filter: keep a host whose estimate reaches the threshold (lane 0 appends).
-__device__ __forceinline__ void keep_if_super(const Dev& d, const sps_result& res,
-                                              double threshold) {
-  if (lane_id() == 0 && res.estimate >= threshold) {
-    const uint32_t pos = atomicAdd(&d.ctrl->n_kept, 1u);
-    if (pos < d.cand_cap) d.kept[pos] = res;
-  }
-}
-
-// Hot extensions of a node (Alg. 4-5 check, in bulk).  Row i's SRE for the extension t is
-// he0 ^ B(i): its low q-delta bits are `low` (B(i)'s low bits xor he0's, from bits already
-// fixed) and its top delta bits are u = t ^ top0 (top0: he0's top bits).  The transposed
-// table keeps, for each (row, low), the 2^delta hot bits over u in one entry; the result is
-// that entry, indexed by u (the caller maps u back to t = u ^ top0).
-__device__ __forceinline__ uint32_t hot_tops(const uint32_t* __restrict__ tb, uint32_t q,
-                                             uint32_t dl, uint32_t wmask, uint32_t row,
-                                             uint32_t low) {
-  const uint32_t pos = (row << q) + (low << dl);
-  return (tb[pos >> 5] >> (pos & 31u)) & wmask;
-}
-
-// The extensions allowed by bit 32 (t < 2^f, see fit_mask) as a mask over u = t ^ top0: a
-// block of 2^f consecutive u values starting at top0 with its low f bits cleared.
-__device__ __forceinline__ uint32_t fit_tops(uint32_t sx, uint32_t dl, uint32_t wmask,
-                                             uint32_t top0) {
-  const uint32_t f = sx >= 32u ? 0u : (32u - sx < dl ? 32u - sx : dl);
-  if (f == dl) return wmask;
-  const uint32_t blk = 1u << f;  // <= 16 here
-  return ((1u << blk) - 1u) << (top0 & ~(blk - 1u));
-}
-
-// Extensions t of row i whose bits stay below bit 32 (bit positions [(i-2)delta + q, ...)).
-__host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i) {
-  const uint32_t sh = (i - 2u) * dl + q;
-  const uint32_t width = 1u << dl;
-  if (sh >= 32u) return 1u;
-  const uint32_t free_bits = 32u - sh;
-  if (free_bits >= dl) return width == 32u ? 0xFFFFFFFFu : ((1u << width) - 1u);
-  return (1u << (1u << free_bits)) - 1u;
-}
-
-// Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  A pair (he0, he1) of hot SREs of
-// rows 0 and 1 fixes B(1) = he0 ^ he1, the address bits [0, q).  Row i >= 2 adds the delta
-// bits [(i-2)delta + q, (i-1)delta + q); the overlap of B(i) with B(i-1) holds by
-// construction, so an extension survives when SRE he0 ^ B(i) of row i is hot and no bit at
-// or above 32 is set.  Each node's surviving extensions come from one load of the
-// transposed hot table.  A full tuple is kept when RHFG[0] of the address is he0.
-//
-// Work: every wave runs its own search with a stack of nodes in LDS.  A node is
-// (x, he0, i): the address bits fixed so far, the row-0 SRE and the next row to extend.
-// Each iteration the wave takes up to 64 nodes from the top of its stack, tops the batch
-// up with fresh (he0, he1) pairs when the stack holds fewer than 64, expands all of them at
-// once (one node per lane) and pushes the children; nodes at the last row check their
-// extensions in place.  Children of lanes nearer the top are pushed above the others, so
-// the stack stays ordered by row from bottom to top and stays small: a batch that reaches
-// into the nodes of row i takes every node above row i with it, so no row holds more than
-// 64 times the extensions of one node.  That bound (64 * sum_i |extensions of row i|, 2048
-// entries at q = 14, delta = 2) would cost so much LDS that few waves fit on a compute unit,
-// so the stack is smaller (join_stack_entries); when a batch's children do not fit, each
-// lane instead searches its own node's subtree depth first in registers (join_lane_dfs)
-// and nothing is pushed.  Either way every node is expanded exactly once.
-//
-// Pairs are numbered a * n1 + b and cut into groups of 64; wave w of W takes groups w,
-// w + W, w + 2W, ... in order (no shared counter).  Lane j keeps the (a, b) of slot j of the
-// wave's current group; a lane taking a pair reads its coordinates from the owning slot
-// (one cross-lane move), and the next group's are the same advanced by 64 W pairs.  The
-// hot table, the stacks and (when they fit) the two hot lists live in LDS, so the loop
-// touches no global memory except to record a candidate.
-constexpr uint32_t kLdsBytes = 160u << 10;  // LDS of one gfx950 compute unit
-constexpr uint32_t kJoinWaves = 16;        // waves per block at most
-
-__host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
-#ifdef __HIP_DEVICE_COMPILE__
-  return __popc(v);
-#else
-  return (uint32_t)__builtin_popcount(v);
-#endif
-}
-
-// Stack entries per wave: room for a full batch of children (64 nodes x 2^delta) on top of
-// what the stack usually holds.
-uint32_t join_stack_entries(uint32_t dl) {
-  const uint32_t need = 64u * (1u << dl) + 64u;
-  return need > 768u ? need : 768u;
-}
-
-// Hot lists as read by the join: u16 entries in LDS when q <= 16, else u32 (global).
-template <typename T>
-struct HotLists {
-  const T* l0;
-  const T* l1;
-  __device__ __forceinline__ uint32_t he0(uint32_t a) const { return l0[a]; }
-  __device__ __forceinline__ uint32_t he1(uint32_t b) const { return l1[b]; }
-};
-
-// a = p / n1, b = p % n1 from a double-precision estimate corrected by one step (the
-// estimate is off by less than one: p < 2^48 and rcp = 1/n1 to 53 bits).
-template <bool kSmall>
-__device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp, uint32_t& a,
-                                            uint32_t& b) {
-  if (kSmall) {  // p < 2^32, n0 and n1 < 2^24: the quotient and n1 fit 24-bit factors
-    const uint32_t p32 = (uint32_t)p;
-    const uint32_t q0 = (uint32_t)((double)p32 * rcp);
-    const int32_t rem = (int32_t)(p32 - __umul24(q0, n1));
-    const bool neg = rem < 0, over = rem >= (int32_t)n1;
-    a = neg ? q0 - 1u : (over ? q0 + 1u : q0);
-    b = (uint32_t)(neg ? rem + (int32_t)n1 : (over ? rem - (int32_t)n1 : rem));
-  } else {
-    uint64_t q0 = (uint64_t)((double)p * rcp);
-    int64_t rem = (int64_t)(p - q0 * n1);
-    if (rem < 0) {
-      --q0;
-      rem += n1;
-    } else if ((uint64_t)rem >= n1) {
-      ++q0;
-      rem -= n1;
-    }
-    a = (uint32_t)q0;
-    b = (uint32_t)rem;
-  }
-}
-
-// Subtree search of one lane, with the partial address as its only state: used when a
-// wave's stack has no room for a batch's children.  (x, he0, i) is a node whose row-i
-// extensions (over u = t ^ top0) are R; every descendant is visited once, depth first:
-// backing up from row i to row i-1 clears row i-1's extension bits from x and recomputes
-// row i-1's extensions above the one just finished.
-__device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
-                                               uint32_t wmask, uint32_t lowmask, uint32_t qmask,
-                                               uint32_t x, uint32_t he0, uint32_t i, uint32_t R,
-                                               bool fuse) {
-  const uint32_t q = d.q, dl = d.delta, r = d.r;
-  const uint32_t top0 = he0 >> (q - dl), dmask = (1u << dl) - 1u;
-  const uint32_t i0 = i;
-  uint32_t expanded = 0;  // nodes expanded below (x, he0, i)
-  for (;;) {
-    if (R == 0u) {
-      if (i == i0) return expanded;
-      --i;  // back up: the extension taken at row i
-      const uint32_t sx = (i - 2u) * dl + q;
-      const uint32_t t = sx < 32u ? (x >> sx) & dmask : 0u;
-      if (sx < 32u) x &= (1u << sx) - 1u;
-      const uint32_t u = t ^ top0;
-      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
-      const uint32_t above = u >= 31u ? 0u : ~((2u << u) - 1u);
-      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sx, dl, wmask, top0) & above;
-      continue;
-    }
-    const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
-    R &= R - 1u;
-    const uint32_t sx = (i - 2u) * dl + q;
-    const uint32_t xi = sx < 32u ? x | (t << sx) : x;
-    if (i + 1u == r) {
-      if ((fmix32(xi ^ d.seed_rhfg0) & qmask) == he0) {
-        const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-        if (pos < d.cand_cap) d.cand[pos] = xi;
-        if (fuse) {  // estimated later by the sort kernel
-          const uint32_t pp = atomicAdd(&d.ctrl->n_pend, 1u);
-          if (pp < d.cand_cap) d.pend[pp] = xi;
-        }
-      }
-    } else {
-      x = xi;
-      ++i;
-      ++expanded;
-      const uint32_t sxn = (i - 2u) * dl + q;
-      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
-      R = hot_tops(tb, q, dl, wmask, i, low) & fit_tops(sxn, dl, wmask, top0);
-    }
-  }
-}
-
-// What the join needs to estimate the candidates it finds (fuse != 0): the scan's slice, the
-// window's oldest live stamp and the threshold.
-struct EstArgs {
-  uint32_t cur, lo, fuse, pad;
-  double threshold;
-};
-
-// kFullFit: every row's extensions stay below bit 32 ((r-2) delta + q <= 32), so the
-// bit-32 limit never removes an extension and extension bits always shift in range.
-template <bool kSmall, bool kFullFit, typename L>
-__device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
-                                          u32x2* __restrict__ stk, uint32_t cap, L lists,
-                                          uint32_t n0, uint32_t n1, const EstArgs& ea) {
-  const uint32_t q = d.q, dl = d.delta, r = d.r;
-  const uint64_t pairs = (uint64_t)n0 * n1;
-  const uint32_t lane = lane_id();
-  const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
-  const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
-  const double rcp = 1.0 / (double)n1;
-
-  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
-  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  const uint64_t stride = 64ull * n_waves;  // pairs between a wave's groups
-  uint64_t g_first = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + wib) * 64ull;
-  auto group_n = [pairs](uint64_t first) -> uint32_t {
-    return first < pairs ? (pairs - first < 64ull ? (uint32_t)(pairs - first) : 64u) : 0u;
-  };
-  uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
-  // (a, b) of the first pair of the current and of the next group (uniform); with n1 >= 128 a
-  // lane's pair is at most 126 further on, one step past the end of row a at most
-  const bool near = n1 >= 128u;
-  const uint32_t step_a = (uint32_t)(stride / n1), step_b = (uint32_t)(stride % n1);
-  uint32_t ca = (uint32_t)(g_first / n1), cb = (uint32_t)(g_first % n1);
-  uint32_t na = ca + step_a, nb = cb + step_b;
-  if (nb >= n1) {
-    nb -= n1;
-    ++na;
-  }
-  uint32_t used = 0;  // pairs of the current group already taken (uniform)
-  uint32_t size = 0;  // nodes on this wave's stack (uniform)
-  uint32_t nodes = 0;  // nodes this wave expanded (uniform; at most a few times 10^5)
-  double P = -1.0;     // product of the row setting factors, read at the first candidate
-  for (;;) {
-    const uint32_t popped = size < 64u ? size : 64u;
-    const uint32_t need = 64u - popped;
-    const uint32_t t1 = cur_n - used < need ? cur_n - used : need;  // from the current group
-    const uint32_t t2 = nxt_n < need - t1 ? nxt_n : need - t1;      // then from the next
-    if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
-    const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
-    uint32_t x = 0, he0 = 0, i = 2, R = 0;
-    if (lane < popped) {
-      const u32x2 nd = stk[size - 1u - lane];
-      x = nd.x;
-      he0 = nd.y & 0xFFFFFFu;
-      i = nd.y >> 24;
-    } else if (k < t1 + t2) {
-      uint32_t a, b;
-      if (near) {
-        a = k < t1 ? ca : na;
-        b = k < t1 ? cb + used + k : nb + (k - t1);
-        if (b >= n1) {
-          b -= n1;
-          ++a;
-        }
-      } else {
-        pair_coords<kSmall>(g_first + (k < t1 ? used + k : stride + (k - t1)), n1, rcp, a, b);
-      }
-      he0 = lists.he0(a);
-      x = he0 ^ lists.he1(b);
-    }
-    const uint32_t top0 = he0 >> (q - dl);
-    const uint32_t sx = __umul24(i - 2u, dl) + q;  // first bit of the extension
-    const bool active = lane < popped + t1 + t2;
-    const bool full_tuple = i == r;  // a complete address: check RHFG[0] of it against he0
-    bool found = false;
-    if (active) {
-      if (full_tuple) {
-        found = (fmix32(x ^ d.seed_rhfg0) & qmask) == he0;
-      } else {
-        const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
-        R = hot_tops(tb, q, dl, wmask, i, low);
-        if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
-      }
-    }
-    nodes += (uint32_t)__popcll(__ballot(active && !full_tuple));
-    if (found) {
-      const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-      if (pos < d.cand_cap) d.cand[pos] = x;
-    }
-    if (ea.fuse) {  // the whole wave estimates each candidate found in this batch (uniform)
-      uint64_t fm = __ballot(found);
-      while (fm) {
-        const int l = __builtin_ctzll(fm);
-        fm &= fm - 1ull;
-        if (P < 0.0) P = row_factor_product(d);
-        const uint32_t cx = __builtin_amdgcn_readlane(x, l);
-        keep_if_super(d, estimate_host<false>(d, cx, ea.cur, ea.lo, ea.threshold, P, MlpRef{}),
-                      ea.threshold);
-      }
-    }
-    used += t1;
-    if (used == cur_n && nxt_n != 0u) {  // move on to the next group
-      g_first += stride;
-      cur_n = nxt_n;
-      nxt_n = group_n(g_first + stride);
-      used = t2;
-      ca = na;
-      cb = nb;
-      na += step_a;
-      nb += step_b;
-      if (nb >= n1) {
-        nb -= n1;
-        ++na;
-      }
-    }
-    const uint32_t c = popc32(R);  // children to push (complete addresses at the last row)
-    const uint32_t incl = wave_incl_scan(c);
-    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-    const uint32_t below = incl - c;
-    const uint32_t base = size - popped;
-    if (base + total <= cap) {  // uniform: the children fit on the stack
-      uint32_t pos = base + total - below;  // this lane's children end here
-      const uint32_t meta = he0 | ((i + 1u) << 24);
-      while (R) {
-        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
-        R &= R - 1u;
-        const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
-        if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
-      }
-      size = base + total;
-    } else {  // no room: every lane searches its own node's subtree depth first instead
-      const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R, ea.fuse != 0u);
-      nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
-      size = base;
-    }
-  }
-  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
-}
-
-// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
-template <bool kTbLds>
-__global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
-                                                          uint32_t list_words, EstArgs ea) {
-  extern __shared__ uint32_t sh[];
-  const uint32_t q = d.q, r = d.r;
-  const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
-  if (n0 == 0u || n1 == 0u) return;
-  const uint32_t* __restrict__ tb = d.hot_t;
-  uint32_t off = 0;
-  if (kTbLds) {
-    const uint32_t words = (r << q) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
-    tb = sh;
-    off = words;  // even: q >= 6
-  }
-  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
-  uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
-  const uint32_t* g0 = d.hse;
-  const uint32_t* g1 = d.hse + (1u << q);
-  // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
-  const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull && n0 < (1u << 24) && n1 < (1u << 24);
-  const bool full = (r - 2u) * d.delta + q <= 32u;
-  auto run = [&](auto lists) {
-    if (small && full)
-      join_wave<true, true>(d, tb, stk, cap, lists, n0, n1, ea);
-    else if (small)
-      join_wave<true, false>(d, tb, stk, cap, lists, n0, n1, ea);
-    else if (full)
-      join_wave<false, true>(d, tb, stk, cap, lists, n0, n1, ea);
-    else
-      join_wave<false, false>(d, tb, stk, cap, lists, n0, n1, ea);
-  };
-  if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
-    uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
-    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
-    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
-    __syncthreads();
-    run(HotLists<uint16_t>{h, h + n0});
-  } else {
-    __syncthreads();
-    run(HotLists<uint32_t>{g0, g1});
-  }
-}
-
-// Launch shape of the join: one block per compute unit with as many waves (up to 16) as the
-// LDS holds after the hot table (when it is small) and a reserve for the hot lists; the lists
-// take whatever LDS is left.  (Two blocks of 10 waves per CU, with smaller stacks, measured
-// 7 % slower at the config-2 shape than one block of 16.)
-struct JoinShape {
-  bool tb_lds;
-  uint32_t cap, waves, lds, blocks, list_words;
-};
-
-JoinShape join_shape(const Dev& d, int n_cu) {
-  JoinShape s{};
-  s.cap = join_stack_entries(d.delta);
-  const uint32_t stack = s.cap * 8u;  // at most 16.5 KiB
-  const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
-  const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
-  s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
-  const uint32_t fixed = s.tb_lds ? tb : 0u;
-  s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
-  if (s.waves > kJoinWaves) s.waves = kJoinWaves;
-  if (s.waves < 1u) s.waves = 1u;
-  s.lds = kLdsBytes;
-  s.blocks = (uint32_t)n_cu;
-  s.list_words = (s.lds - fixed - s.waves * stack) / 4u;
-  return s;
-}
-
-hipError_t prepare_join() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-}
-
 // Stage 4: order the kept hosts ascending.  Up to kSortTile hosts: a bitonic sort of (host,
 // index) keys, padded to a power of two with keys above every host (in registers and
 // cross-lane moves up to 1024 hosts, in LDS beyond).  More: a
@@ -1019,30 +928,11 @@ constexpr int kSortTile = 4096;
 
 __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
                                                             uint32_t cap,
-                                                            uint32_t* __restrict__ info,
-                                                            uint32_t cur, uint32_t lo,
-                                                            double threshold) {
+                                                            uint32_t* __restrict__ info) {
   __shared__ uint64_t key[kSortTile];
   uint32_t* const tile = reinterpret_cast<uint32_t*>(key);
   Ctrl* c = d.ctrl;
-  // candidates the join listed without estimating them (its depth-first fallback), one per
-  // wave; then the transposed hot table is cleared for the next scan
-  const uint32_t n_pend = min(c->n_pend, d.cand_cap);
-  if (n_pend) {
-    const double P = row_factor_product(d);
-    for (uint32_t j = threadIdx.x / kWave; j < n_pend; j += blockDim.x / kWave) {
-      const uint32_t x = __builtin_amdgcn_readfirstlane(d.pend[j]);
-      keep_if_super(d, estimate_host<false>(d, x, cur, lo, threshold, P, MlpRef{}), threshold);
-    }
-  }
-  {
-    const uint32_t words = (d.r << d.q) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) d.hot_t[w] = 0;
-  }
-  __syncthreads();
-  // read back through the atomic unit: this block's own appends above went there
-  const uint32_t n_kept = atomicAdd(&c->n_kept, 0u);
-  const uint32_t n = min(n_kept, d.cand_cap);
+  const uint32_t n = min(c->n_kept, d.cand_cap);
   if (out && n <= (uint32_t)kSortThreads) {
     // one key per thread; partners closer than 64 are in the same wave (cross-lane moves),
     // farther ones go through LDS
@@ -1113,10 +1003,9 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
   __syncthreads();
   if (threadIdx.x == 0) {
     if (info) {
-      info[SPS_INFO_KEPT] = n_kept;
+      info[SPS_INFO_KEPT] = c->n_kept;
       info[SPS_INFO_CAND] = c->n_cand;
-      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap || c->n_pend > d.cand_cap ? 1u : 0u) |
-                             (n_kept > cap ? 2u : 0u);
+      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
       info[SPS_INFO_HSE0] = c->hse_count[0];
       info[SPS_INFO_HSE1] = c->hse_count[1];
       info[SPS_INFO_NODES_LO] = (uint32_t)c->join_nodes;
@@ -1133,10 +1022,10 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
   for (uint32_t i = threadIdx.x; i < kCtrlWorkingWords; i += blockDim.x) w[i] = 0;
 }
 
-// Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter) as its own pass: one wave per candidate.
-// Used by scans with the learned estimator attached (the join then only lists the
-// candidates) and, with a host list (`hosts` non-null), to estimate given hosts, each
-// written to direct[c] unfiltered.
+// Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.  With a host
+// list (`hosts` non-null) every host is estimated and written to direct[c] unfiltered.
+// In a scan the blocks also clear the join's table (the join has finished) for the next
+// scan.
 __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t lo, uint32_t k,
                                                   double threshold, MlpRef mlp,
                                                   const uint32_t* __restrict__ hosts,
@@ -1144,17 +1033,66 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
                                                   sps_result* __restrict__ direct) {
   const uint32_t n = hosts ? n_hosts : min(d.ctrl->n_cand, d.cand_cap);
   const uint32_t* __restrict__ src = hosts ? hosts : d.cand;
+  if (!hosts) {
+    const uint32_t words = (d.r << d.q) >> 5;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x)
+      d.hot_t[w] = 0;
+  }
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  const uint32_t lane = lane_id();
   const bool use_mlp = mlp.w != nullptr && k == SPS_MLP_IN;
-  const double P = row_factor_product(d);
+  const uint32_t nfeat = use_mlp ? SPS_MLP_IN : 0u;
+  double P = 1.0;  // product of the row setting factors SF(i, k), rows in order
+  for (uint32_t i = 0; i < d.rp; ++i)
+    P = P * ((double)d.ctrl->row_live[i] / (double)d.row_len);
   for (uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; c < n; c += waves) {
     const uint32_t x = __builtin_amdgcn_readfirstlane(src[c]);
-    const sps_result res = use_mlp ? estimate_host<true>(d, x, cur, lo, threshold, P, mlp)
-                                   : estimate_host<false>(d, x, cur, lo, threshold, P, mlp);
-    if (direct) {
-      if (lane_id() == 0) direct[c] = res;
-    } else {
-      keep_if_super(d, res, threshold);
+    uint32_t U, feat;
+    usle_counts(d, x, cur, lo, nfeat, U, feat);
+    const double etap = (double)d.etap;
+    double w;
+    uint32_t flags = 0;
+    if (P >= 1.0)
+      w = (double)U;
+    else
+      w = ((double)U - etap * P) / (1.0 - P);
+    if (w < 0.0) {
+      w = 0.0;
+      flags |= SPS_F_CLAMPLOW;
+    }
+    if (w > etap - 1.0) {
+      w = etap - 1.0;
+      flags |= SPS_F_SATURATED;
+    }
+    double est = -etap * log1p(-w / etap);
+    if (use_mlp) {
+      // the network replaces linear counting only inside its validated domain
+      const float f = lane < SPS_MLP_IN ? (float)feat / (float)d.etap : 0.f;
+      const bool in_range = lane >= SPS_MLP_IN || (f >= mlp.lo[lane] && f <= mlp.hi[lane]);
+      const bool all_in = __ballot(!in_range) == 0;
+      const bool informative = __shfl(feat, 0, kWave) < d.etap - 1u;
+      const float y = mlp_forward_wave(mlp.w, lane < SPS_MLP_IN ? mlp_encode(feat, d.etap) : 0.f);
+      if (U >= mlp.min_live && all_in && informative && y >= 0.f && y <= mlp.log_max) {
+        est = (double)expf(y);
+        flags |= SPS_F_MLP;
+      } else {
+        flags |= SPS_F_LC_FALLBACK;
+      }
+    }
+    if (fabs(est - threshold) <= 1e-9 * threshold) flags |= SPS_F_NEAR;
+    if (lane == 0) {
+      sps_result res;
+      res.host = x;
+      res.live = U;
+      res.flags = flags;
+      res.pad = 0;
+      res.estimate = est;
+      if (direct) {
+        direct[c] = res;
+      } else if (est >= threshold) {
+        const uint32_t pos = atomicAdd(&d.ctrl->n_kept, 1u);
+        if (pos < d.cand_cap) d.kept[pos] = res;
+      }
     }
   }
 }
@@ -1164,9 +1102,6 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
                        int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // with the learned estimator in use the candidates are estimated in their own pass;
-  // otherwise the join estimates them as it finds them
-  const bool fuse = !(mlp.w != nullptr && window == SPS_MLP_IN);
   // one block per CU: the SLE array streamed, then one SRE per lane for the hot SREs
   {
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
@@ -1175,27 +1110,21 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
     const JoinShape js = join_shape(d, n_cu);
-    EstArgs ea{};
-    ea.cur = cur;
-    ea.lo = lo;
-    ea.fuse = fuse ? 1u : 0u;
-    ea.threshold = threshold;
     if (js.tb_lds)
       hipLaunchKernelGGL(k_join<true>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
-                         js.cap, js.list_words, ea);
+                         js.cap, js.list_words);
     else
       hipLaunchKernelGGL(k_join<false>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
-                         js.cap, js.list_words, ea);
+                         js.cap, js.list_words);
   }
-  if (!fuse) {
+  {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
     hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
                        threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr);
   }
   {
     ProfScope ps(SPS_STAGE_SORT, st);
-    hipLaunchKernelGGL(k_rank_sort, dim3(1), dim3(kSortThreads), 0, st, d, out, cap, info, cur,
-                       lo, threshold);
+    hipLaunchKernelGGL(k_rank_sort, dim3(1), dim3(kSortThreads), 0, st, d, out, cap, info);
   }
   return hipGetLastError();
 }
