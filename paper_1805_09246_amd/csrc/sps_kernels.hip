@@ -623,34 +623,31 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
     nodes += popped + t1 + t2;
     const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
-    uint32_t x = 0, he0 = 0, i = 2, R = 0;
-    if (lane < popped) {
-      const u32x2 nd = stk[size - 1u - lane];
-      x = nd.x;
-      he0 = nd.y & 0xFFFFFFu;
-      i = nd.y >> 24;
-    } else if (k < t1 + t2) {
-      uint32_t a, b;
-      if (near) {
-        a = k < t1 ? ca : na;
-        b = k < t1 ? cb + used + k : nb + (k - t1);
-        if (b >= n1) {
-          b -= n1;
-          ++a;
-        }
-      } else {
-        pair_coords<kSmall>(g_first + (k < t1 ? used + k : stride + (k - t1)), n1, rcp, a, b);
-      }
-      he0 = lists.he0(a);
-      x = he0 ^ lists.he1(b);
+    // Every lane reads both a stack entry and a pair and keeps the one its role asks for:
+    // the reads are issued once per wave either way, and no exec-mask branches are needed.
+    const bool pop = lane < popped;
+    const bool fresh = !pop && k < t1 + t2;
+    const u32x2 nd = stk[pop ? size - 1u - lane : 0u];
+    uint32_t a, b;
+    if (near) {  // uniform
+      a = k < t1 ? ca : na;
+      b = k < t1 ? cb + used + k : nb + (k - t1);
+      const bool wrap = b >= n1;
+      a = wrap ? a + 1u : a;
+      b = wrap ? b - n1 : b;
+    } else {
+      pair_coords<kSmall>(g_first + (k < t1 ? used + k : stride + (k - t1)), n1, rcp, a, b);
     }
+    const uint32_t phe0 = lists.he0(fresh ? a : 0u), phe1 = lists.he1(fresh ? b : 0u);
+    const uint32_t x = pop ? nd.x : (fresh ? phe0 ^ phe1 : 0u);
+    const uint32_t he0 = pop ? nd.y & 0xFFFFFFu : (fresh ? phe0 : 0u);
+    const uint32_t i = pop ? nd.y >> 24 : 2u;
     const uint32_t top0 = he0 >> (q - dl);
     const uint32_t sx = __umul24(i - 2u, dl) + q;  // first bit of the extension
-    if (lane < popped + t1 + t2) {
-      const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
-      R = hot_tops(tb, q, dl, wmask, i, low);
-      if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
-    }
+    const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
+    uint32_t R = hot_tops(tb, q, dl, wmask, i, low);
+    if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
+    R = pop || fresh ? R : 0u;
     used += t1;
     if (used == cur_n && nxt_n != 0u) {  // move on to the next group
       g_first += stride;
