@@ -592,6 +592,8 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
   const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
+  const uint32_t dmask = (1u << dl) - 1u;
+  const bool narrow = dl <= 2u;  // uniform
   const double rcp = 1.0 / (double)n1;
 
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
@@ -664,7 +666,19 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       }
     }
     const bool last = i + 1u == r;
-    if (last) {
+    if (narrow) {  // uniform: at most 4 extensions, checked in a fixed-trip loop
+      if (__ballot(last && R != 0u)) {
+        for (uint32_t u = 0; u <= dmask; ++u) {
+          const uint32_t t = u ^ top0;
+          const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
+          if (last && ((R >> u) & 1u) && (fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+            const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+            if (pos < d.cand_cap) d.cand[pos] = addr;
+          }
+        }
+        R = last ? 0u : R;
+      }
+    } else if (last) {
       while (R) {
         const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
@@ -683,11 +697,21 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     if (base + total <= cap) {  // uniform: the children fit on the stack
       uint32_t pos = base + total - below;  // this lane's children end here
       const uint32_t meta = he0 | ((i + 1u) << 24);
-      while (R) {
-        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
-        R &= R - 1u;
-        const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
-        if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
+      if (narrow) {  // every extension stored; those not taken go to the lane's spare entry
+        for (uint32_t u = 0; u <= dmask; ++u) {
+          const bool take = (R >> u) & 1u;
+          pos -= take ? 1u : 0u;
+          const uint32_t t = u ^ top0;
+          const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
+          stk[take && pos < cap ? pos : cap + lane] = child;
+        }
+      } else {
+        while (R) {
+          const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+          R &= R - 1u;
+          const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
+          if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
+        }
       }
       size = base + total;
     } else {  // no room: every lane searches its own node's subtree depth first instead
@@ -699,7 +723,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
 }
 
-// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
+// LDS: [hot table (kTbLds)] [stacks: waves x (cap + 64) entries] [hot lists, list_words words].
 template <bool kTbLds>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                                                           uint32_t list_words) {
@@ -715,8 +739,9 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     tb = sh;
     off = words;  // even: q >= 6
   }
-  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
-  uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
+  // each wave's stack holds cap entries and one spare per lane (see the narrow push)
+  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * (cap + 64u);
+  uint32_t* const lw = sh + off + 2u * (cap + 64u) * (blockDim.x / kWave);
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
   // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
@@ -756,7 +781,7 @@ struct JoinShape {
 JoinShape join_shape(const Dev& d, int n_cu) {
   JoinShape s{};
   s.cap = join_stack_entries(d.delta);
-  const uint32_t stack = s.cap * 8u;  // at most 16.5 KiB
+  const uint32_t stack = (s.cap + 64u) * 8u;  // cap entries and a spare per lane; <= 17 KiB
   const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
   const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
@@ -822,36 +847,44 @@ __device__ __forceinline__ void usle_counts(const Dev& d, uint32_t x, uint32_t c
       }
     }
   } else if (vec) {
-    for (uint32_t z0 = 0; z0 < d.etap; z0 += 8 * kWave) {
-      const uint32_t z = z0 + lane * 8;
-      if (z < d.etap) {
-        u32x4 v[kMaxRP];
+    // two passes of 8 cells per lane at a time: all rows' loads of both passes in flight
+    auto count8 = [&](const u32x4* v) {
+      uint32_t m[8];
 #pragma unroll
-        for (int i = 0; i < kMaxRP; ++i)
-          if (i < (int)d.rp) v[i] = *reinterpret_cast<const u32x4*>(d.slea + base[i] + z);
-        uint32_t m[8];
+      for (int k = 0; k < 8; ++k) m[k] = 0xFFFFu;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) m[k] = 0xFFFFu;
+      for (int i = 0; i < kMaxRP; ++i) {
+        if (i < (int)d.rp) {
 #pragma unroll
-        for (int i = 0; i < kMaxRP; ++i) {
-          if (i < (int)d.rp) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              const uint32_t w = k < 2 ? v[i].x : (k < 4 ? v[i].y : (k < 6 ? v[i].z : v[i].w));
-              const uint32_t c = (k & 1) ? w >> 16 : w & 0xFFFFu;
-              m[k] = c < m[k] ? c : m[k];
-            }
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          c_live += m[k] >= lo;  // lo >= 1, so never-written cells are not live
-          for (uint32_t a = 0; a < nfeat; ++a) {
-            const uint32_t lo_a = cur > a + 1u ? cur - a : 1u;
-            c_age[a] += m[k] >= lo_a;
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t w = k < 2 ? v[i].x : (k < 4 ? v[i].y : (k < 6 ? v[i].z : v[i].w));
+            const uint32_t c = (k & 1) ? w >> 16 : w & 0xFFFFu;
+            m[k] = c < m[k] ? c : m[k];
           }
         }
       }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        c_live += m[k] >= lo;  // lo >= 1, so never-written cells are not live
+        for (uint32_t a = 0; a < nfeat; ++a) {
+          const uint32_t lo_a = cur > a + 1u ? cur - a : 1u;
+          c_age[a] += m[k] >= lo_a;
+        }
+      }
+    };
+    for (uint32_t z0 = 0; z0 < d.etap; z0 += 16 * kWave) {
+      const uint32_t za = z0 + lane * 8, zb = za + 8 * kWave;
+      const bool ina = za < d.etap, inb = zb < d.etap;
+      u32x4 va[kMaxRP], vb[kMaxRP];
+#pragma unroll
+      for (int i = 0; i < kMaxRP; ++i) {
+        if (i < (int)d.rp) {
+          if (ina) va[i] = *reinterpret_cast<const u32x4*>(d.slea + base[i] + za);
+          if (inb) vb[i] = *reinterpret_cast<const u32x4*>(d.slea + base[i] + zb);
+        }
+      }
+      if (ina) count8(va);
+      if (inb) count8(vb);
     }
   } else {
     for (uint32_t z0 = 0; z0 < d.etap; z0 += kWave) {
@@ -1042,8 +1075,11 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
   double P = 1.0;  // product of the row setting factors SF(i, k), rows in order
   for (uint32_t i = 0; i < d.rp; ++i)
     P = P * ((double)d.ctrl->row_live[i] / (double)d.row_len);
-  for (uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; c < n; c += waves) {
-    const uint32_t x = __builtin_amdgcn_readfirstlane(src[c]);
+  const uint32_t c0 = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  // the first host is read before the count is known (in bounds: c0 < the list's capacity)
+  const uint32_t x0 = c0 < (hosts ? n_hosts : d.cand_cap) ? src[c0] : 0u;
+  for (uint32_t c = c0; c < n; c += waves) {
+    const uint32_t x = __builtin_amdgcn_readfirstlane(c == c0 ? x0 : src[c]);
     uint32_t U, feat;
     usle_counts(d, x, cur, lo, nfeat, U, feat);
     const double etap = (double)d.etap;
