@@ -592,8 +592,6 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
   const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
-  const uint32_t dmask = (1u << dl) - 1u;
-  const bool narrow = dl <= 2u;  // uniform
   const double rcp = 1.0 / (double)n1;
 
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
@@ -666,19 +664,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       }
     }
     const bool last = i + 1u == r;
-    if (narrow) {  // uniform: at most 4 extensions, checked in a fixed-trip loop
-      if (__ballot(last && R != 0u)) {
-        for (uint32_t u = 0; u <= dmask; ++u) {
-          const uint32_t t = u ^ top0;
-          const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
-          if (last && ((R >> u) & 1u) && (fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
-            const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-            if (pos < d.cand_cap) d.cand[pos] = addr;
-          }
-        }
-        R = last ? 0u : R;
-      }
-    } else if (last) {
+    if (last) {
       while (R) {
         const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
@@ -697,21 +683,11 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     if (base + total <= cap) {  // uniform: the children fit on the stack
       uint32_t pos = base + total - below;  // this lane's children end here
       const uint32_t meta = he0 | ((i + 1u) << 24);
-      if (narrow) {  // every extension stored; those not taken go to the lane's spare entry
-        for (uint32_t u = 0; u <= dmask; ++u) {
-          const bool take = (R >> u) & 1u;
-          pos -= take ? 1u : 0u;
-          const uint32_t t = u ^ top0;
-          const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
-          stk[take && pos < cap ? pos : cap + lane] = child;
-        }
-      } else {
-        while (R) {
-          const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
-          R &= R - 1u;
-          const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
-          if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
-        }
+      while (R) {
+        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+        R &= R - 1u;
+        const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
+        if (--pos < cap) stk[pos] = child;  // always true; keeps every store inside the stack
       }
       size = base + total;
     } else {  // no room: every lane searches its own node's subtree depth first instead
@@ -723,7 +699,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
 }
 
-// LDS: [hot table (kTbLds)] [stacks: waves x (cap + 64) entries] [hot lists, list_words words].
+// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
 template <bool kTbLds>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                                                           uint32_t list_words) {
@@ -739,9 +715,8 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     tb = sh;
     off = words;  // even: q >= 6
   }
-  // each wave's stack holds cap entries and one spare per lane (see the narrow push)
-  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * (cap + 64u);
-  uint32_t* const lw = sh + off + 2u * (cap + 64u) * (blockDim.x / kWave);
+  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
+  uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
   // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
@@ -781,7 +756,7 @@ struct JoinShape {
 JoinShape join_shape(const Dev& d, int n_cu) {
   JoinShape s{};
   s.cap = join_stack_entries(d.delta);
-  const uint32_t stack = (s.cap + 64u) * 8u;  // cap entries and a spare per lane; <= 17 KiB
+  const uint32_t stack = s.cap * 8u;  // at most 16.5 KiB
   const uint32_t tb = (uint32_t)((((uint64_t)d.r << d.q) >> 5) * 4);
   const uint32_t reserve = 16u << 10;  // 8 Ki u16 list entries at least, when they fit
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
