@@ -435,24 +435,16 @@ __device__ __forceinline__ uint32_t hot_tops(const uint32_t* __restrict__ tb, ui
   return (tb[pos >> 5] >> (pos & 31u)) & wmask;
 }
 
-// The extensions allowed by bit 32 (t < 2^f, see fit_mask) as a mask over u = t ^ top0: a
-// block of 2^f consecutive u values starting at top0 with its low f bits cleared.
+// The extensions allowed by bit 32 as a mask over u = t ^ top0.  Row i's new bits start at
+// sx = (i-2) delta + q; only the f = min(32 - sx, delta) low ones can be set (f = 0 when
+// sx >= 32), so t < 2^f: a block of 2^f consecutive u values starting at top0 with its low
+// f bits cleared.
 __device__ __forceinline__ uint32_t fit_tops(uint32_t sx, uint32_t dl, uint32_t wmask,
                                              uint32_t top0) {
   const uint32_t f = sx >= 32u ? 0u : (32u - sx < dl ? 32u - sx : dl);
   if (f == dl) return wmask;
   const uint32_t blk = 1u << f;  // <= 16 here
   return ((1u << blk) - 1u) << (top0 & ~(blk - 1u));
-}
-
-// Extensions t of row i whose bits stay below bit 32 (bit positions [(i-2)delta + q, ...)).
-__host__ __device__ __forceinline__ uint32_t fit_mask(uint32_t q, uint32_t dl, uint32_t i) {
-  const uint32_t sh = (i - 2u) * dl + q;
-  const uint32_t width = 1u << dl;
-  if (sh >= 32u) return 1u;
-  const uint32_t free_bits = 32u - sh;
-  if (free_bits >= dl) return width == 32u ? 0xFFFFFFFFu : ((1u << width) - 1u);
-  return (1u << (1u << free_bits)) - 1u;
 }
 
 // Stage 2, candidate recovery (Alg. 4-5 through Eq. 6-7).  A pair (he0, he1) of hot SREs of
@@ -784,12 +776,6 @@ hipError_t prepare_join() {
 // rows' loads in flight together); otherwise one cell per lane.  Per-lane counts are summed
 // over the wave once at the end; lane a ends up holding x_a (cells with stamp >=
 // max(1, cur - a)) for a < nfeat, and every lane holds |USLE|^k in `live`.
-__device__ __forceinline__ uint32_t min_u16_pair(uint32_t a, uint32_t b, int hi) {
-  const uint32_t x = hi ? a >> 16 : a & 0xFFFFu;
-  const uint32_t y = hi ? b >> 16 : b & 0xFFFFu;
-  return x < y ? x : y;
-}
-
 __device__ __forceinline__ void usle_counts(const Dev& d, uint32_t x, uint32_t cur, uint32_t lo,
                                             uint32_t nfeat, uint32_t& live, uint32_t& feat) {
   uint64_t base[kMaxRP];
