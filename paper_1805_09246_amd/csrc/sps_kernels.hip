@@ -458,10 +458,9 @@ __device__ __forceinline__ uint32_t fit_tops(uint32_t sx, uint32_t dl, uint32_t 
 // (x, he0, i): the address bits fixed so far, the row-0 SRE and the next row to extend.
 // Each iteration the wave takes up to 64 nodes from the top of its stack, tops the batch
 // up with fresh (he0, he1) pairs when the stack holds fewer than 64, expands all of them at
-// once (one node per lane) and pushes the children; the children of the last row are
-// complete addresses, pushed like the rest and checked one per lane when popped.  Children
-// of lanes nearer the top are pushed above the others, so the stack stays ordered by row
-// from bottom to top and stays small: a batch that reaches
+// once (one node per lane) and pushes the children; nodes at the last row check their
+// extensions in place.  Children of lanes nearer the top are pushed above the others, so
+// the stack stays ordered by row from bottom to top and stays small: a batch that reaches
 // into the nodes of row i takes every node above row i with it, so no row holds more than
 // 64 times the extensions of one node.  That bound (64 * sum_i |extensions of row i|, 2048
 // entries at q = 14, delta = 2) would cost so much LDS that few waves fit on a compute unit,
@@ -614,6 +613,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     const uint32_t t1 = cur_n - used < need ? cur_n - used : need;  // from the current group
     const uint32_t t2 = nxt_n < need - t1 ? nxt_n : need - t1;      // then from the next
     if (popped + t1 + t2 == 0u) break;  // stack empty and no pairs left
+    nodes += popped + t1 + t2;
     const uint32_t k = lane - popped;   // this lane's rank among the fresh pairs
     // Every lane reads both a stack entry and a pair and keeps the one its role asks for:
     // the reads are issued once per wave either way, and no exec-mask branches are needed.
@@ -634,20 +634,12 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
     const uint32_t x = pop ? nd.x : (fresh ? phe0 ^ phe1 : 0u);
     const uint32_t he0 = pop ? nd.y & 0xFFFFFFu : (fresh ? phe0 : 0u);
     const uint32_t i = pop ? nd.y >> 24 : 2u;
-    // an entry of row r is a complete address: one RHFG[0] check per lane, no extensions
-    const bool full_tuple = i == r;
-    const uint32_t ie = full_tuple ? 2u : i;  // row whose table word is read (any valid row)
     const uint32_t top0 = he0 >> (q - dl);
-    const uint32_t sx = __umul24(ie - 2u, dl) + q;  // first bit of the extension
-    const uint32_t low = ((x >> __umul24(ie - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
-    uint32_t R = hot_tops(tb, q, dl, wmask, ie, low);
+    const uint32_t sx = __umul24(i - 2u, dl) + q;  // first bit of the extension
+    const uint32_t low = ((x >> __umul24(i - 1u, dl)) ^ he0) & lowmask;  // (i-1)delta <= 31
+    uint32_t R = hot_tops(tb, q, dl, wmask, i, low);
     if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
-    R = (pop || fresh) && !full_tuple ? R : 0u;
-    nodes += popped + t1 + t2 - (uint32_t)__popcll(__ballot(pop && full_tuple));
-    if (pop && full_tuple && (fmix32(x ^ d.seed_rhfg0) & qmask) == he0) {
-      const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-      if (pos < d.cand_cap) d.cand[pos] = x;
-    }
+    R = pop || fresh ? R : 0u;
     used += t1;
     if (used == cur_n && nxt_n != 0u) {  // move on to the next group
       g_first += stride;
@@ -663,7 +655,19 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
         ++na;
       }
     }
-    const uint32_t c = popc32(R);  // children to push (the last row's are complete addresses)
+    const bool last = i + 1u == r;
+    if (last) {
+      while (R) {
+        const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+        R &= R - 1u;
+        const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
+        if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+          const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+          if (pos < d.cand_cap) d.cand[pos] = addr;
+        }
+      }
+    }
+    const uint32_t c = popc32(R);  // children to push (0 at the last row)
     const uint32_t incl = wave_incl_scan(c);
     const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
     const uint32_t below = incl - c;
