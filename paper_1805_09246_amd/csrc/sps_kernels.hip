@@ -575,12 +575,11 @@ __device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* 
 
 // kFullFit: every row's extensions stay below bit 32 ((r-2) delta + q <= 32), so the
 // bit-32 limit never removes an extension and extension bits always shift in range.
-// kDl: delta known at compile time (2, the workloads' value) or 0 (read from the sketch).
-template <bool kSmall, bool kFullFit, int kDl, typename L>
+template <bool kSmall, bool kFullFit, typename L>
 __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
                                           u32x2* __restrict__ stk, uint32_t cap, L lists,
                                           uint32_t n0, uint32_t n1) {
-  const uint32_t q = d.q, dl = kDl ? (uint32_t)kDl : d.delta, r = d.r;
+  const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint64_t pairs = (uint64_t)n0 * n1;
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
@@ -716,16 +715,14 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull && n0 < (1u << 24) && n1 < (1u << 24);
   const bool full = (r - 2u) * d.delta + q <= 32u;
   auto run = [&](auto lists) {
-    if (small && full && d.delta == 2u)
-      join_wave<true, true, 2>(d, tb, stk, cap, lists, n0, n1);
-    else if (small && full)
-      join_wave<true, true, 0>(d, tb, stk, cap, lists, n0, n1);
+    if (small && full)
+      join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);
     else if (small)
-      join_wave<true, false, 0>(d, tb, stk, cap, lists, n0, n1);
+      join_wave<true, false>(d, tb, stk, cap, lists, n0, n1);
     else if (full)
-      join_wave<false, true, 0>(d, tb, stk, cap, lists, n0, n1);
+      join_wave<false, true>(d, tb, stk, cap, lists, n0, n1);
     else
-      join_wave<false, false, 0>(d, tb, stk, cap, lists, n0, n1);
+      join_wave<false, false>(d, tb, stk, cap, lists, n0, n1);
   };
   if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
     uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
