@@ -84,7 +84,7 @@ def lib():
         L.or_join_brute.restype = C.c_int64
         L.or_join_brute.argtypes = [vp, vp, vp, C.c_uint64, C.c_uint32]
         L.or_join_tuples.restype = C.c_int64
-        L.or_join_tuples.argtypes = [vp, vp, vp, C.c_uint64, C.c_uint64]
+        L.or_join_tuples.argtypes = [vp, vp, vp, C.c_uint64, C.c_uint64, vp]
         L.or_features.argtypes = [vp, C.c_uint32, vp, C.c_uint64, vp]
         L.or_estimate_one.restype = C.c_double
         L.or_estimate_one.argtypes = [vp, C.c_uint32, vp, C.c_double, P(C.c_uint32)]
@@ -211,13 +211,17 @@ class OracleSketch:
             raise RuntimeError(f"join_brute: {n}")
         return out[:n].copy()
 
-    def join_tuples(self, hot: np.ndarray, cap: int = 1 << 22, tuple_cap: int = 1 << 24):
+    def join_tuples(self, hot: np.ndarray, cap: int = 1 << 22, tuple_cap: int = 1 << 24,
+                    levels: bool = False):
+        """Candidates of the tuple-growing search; with levels=True also the tuple count after
+        every row (entry i for row i >= 1; entry 0 unused)."""
         hot = np.ascontiguousarray(hot, dtype=np.uint8)
         out = np.zeros(cap, dtype=np.uint32)
-        n = int(lib().or_join_tuples(self._h, _ptr(hot), _ptr(out), cap, tuple_cap))
+        lv = np.zeros(self.params["r"], dtype=np.uint64)
+        n = int(lib().or_join_tuples(self._h, _ptr(hot), _ptr(out), cap, tuple_cap, _ptr(lv)))
         if n < 0 or n > cap:
             raise RuntimeError(f"join_tuples: {n}")
-        return out[:n].copy()
+        return (out[:n].copy(), lv) if levels else out[:n].copy()
 
     def features(self, k: int, hosts) -> np.ndarray:
         hosts = np.ascontiguousarray(hosts, dtype=np.uint32)

@@ -412,7 +412,9 @@ int64_t or_join_brute(const or_sketch *s, const uint8_t *hot, uint32_t *out, uin
  * equal the low q-delta bits of B(i).  Bits that would lie at or above bit 32 must be zero.
  * After the last row the address is assembled and checked against RHFG[0].
  * hot lists: lists[i] has counts[i] ascending columns.  Returns the count of recovered
- * addresses (ascending after a final sort in the caller), or an error. */
+ * addresses (ascending after a final sort in the caller), or an error.  level_sizes (r
+ * entries, or NULL) receives the number of tuples grown through each row i >= 1: entry 1
+ * counts the pairs (he0, he1) whose B(1) fits 32 bits, entry i the tuples (he0 .. he_i). */
 static int or_cmp_u32(const void *a, const void *b) {
   uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
   return x < y ? -1 : (x > y ? 1 : 0);
@@ -426,7 +428,7 @@ static int or_bits_fit(const or_sketch *s, uint32_t i, uint32_t b) {
 }
 
 int64_t or_join_tuples(const or_sketch *s, const uint8_t *hot, uint32_t *out, uint64_t cap,
-                       uint64_t tuple_cap) {
+                       uint64_t tuple_cap, uint64_t *level_sizes) {
   uint32_t r = s->p.r, q = s->p.q, d = s->p.delta, i;
   uint32_t ncols = 1u << q;
   uint32_t low_mask = (1u << (q - d)) - 1u;
@@ -449,12 +451,15 @@ int64_t or_join_tuples(const or_sketch *s, const uint8_t *hot, uint32_t *out, ui
     free(sctb);
     return OR_ENOMEM;
   }
+  if (level_sizes)
+    for (i = 0; i < r; i++) level_sizes[i] = 0;
   /* Alg. 4: tuples (he0, he1, he2) from rows 0..2, checking B(1) against B(2) */
   for (a = 0; a < counts[0]; a++)
     for (b = 0; b < counts[1]; b++) {
       uint32_t he0 = lists[0][a], he1 = lists[1][b];
       uint32_t B1 = he0 ^ he1;
       if (!or_bits_fit(s, 1, B1)) continue;
+      if (level_sizes) level_sizes[1]++;
       for (c = 0; c < counts[2]; c++) {
         uint32_t he2 = lists[2][c];
         uint32_t B2 = he0 ^ he2;
@@ -467,6 +472,7 @@ int64_t or_join_tuples(const or_sketch *s, const uint8_t *hot, uint32_t *out, ui
         nr++;
       }
     }
+  if (level_sizes && r > 2) level_sizes[2] = nr;
   /* Alg. 5: rows 3..r-1, extending every tuple of the reading buffer by one hot SRE */
   for (i = 3; i < r; i++) {
     ns = 0;
@@ -488,6 +494,7 @@ int64_t or_join_tuples(const or_sketch *s, const uint8_t *hot, uint32_t *out, ui
     rctb = sctb;
     sctb = tmp;
     nr = ns;
+    if (level_sizes) level_sizes[i] = nr;
   }
   /* reconstruct aip from B(1..r-1) and keep it when RHFG[0](aip) is he0 */
   for (m = 0; m < nr; m++) {

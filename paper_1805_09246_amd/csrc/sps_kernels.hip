@@ -691,6 +691,174 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
   if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
 }
 
+// The same search with rows 1-3 taken in bulk (delta = 2, dense rows).  For a row-0 SRE he0
+// and v, the low q - 2 bits of B(4), the prefixes x = j | v << 6 (j: the low 6 address bits)
+// whose windows B(1), B(2), B(3) land on hot SREs he0 ^ B(i) of rows 1-3 form a 64-bit mask
+// over j: B(1) = j | (v << 6 mod 2^q) spans 64 consecutive columns of row 1, B(2) 16
+// columns of row 2 and B(3) 4 of row 3, all XOR-shifted by he0's low bits.  Indexing the
+// mask by j' = j ^ (he0 mod 64), stored with its 2-bit digits reversed (bit p(j') with
+// p = (j' mod 4) * 16 + (j' / 4 mod 4) * 4 + j' / 16), makes row 1's part a plain 64-bit
+// word of a reordered copy of its bitmap, row 2's part a 16-bit pattern repeated 4 times and
+// row 3's a 4-bit pattern repeated 16 times; both patterns only need a XOR permutation of
+// bit positions that is the same for the whole wave (he0 is uniform).  The mask's prefixes
+// are exactly the search's row-3 tuples; one transposed-table entry of row 4 then gives
+// their 2^delta extensions, and the resulting row-4 tuples go on the stack as nodes of
+// row 5 for the ordinary search.  Every v is visited (2^(q-2) per he0), so this pays off
+// only when rows are dense; the caller decides.  The tuples of rows 1-3 that the masks
+// resolve are counted, so the node count is the same as the ordinary search's.
+__device__ __forceinline__ uint32_t xor_perm16(uint32_t x, uint32_t c) {  // bit y <- bit y ^ c
+  if (c & 1u) x = ((x >> 1) & 0x5555u) | ((x & 0x5555u) << 1);
+  if (c & 2u) x = ((x >> 2) & 0x3333u) | ((x & 0x3333u) << 2);
+  if (c & 4u) x = ((x >> 4) & 0x0F0Fu) | ((x & 0x0F0Fu) << 4);
+  if (c & 8u) x = ((x >> 8) & 0x00FFu) | ((x & 0x00FFu) << 8);
+  return x;
+}
+
+// digit-reversed bit position of j' in the 64-bit mask (an involution)
+__host__ __device__ __forceinline__ uint32_t fold_pos(uint32_t j) {
+  return ((j & 3u) << 4) | (j & 12u) | (j >> 4);
+}
+
+struct FoldTables {
+  const u32x2* f1;     // row 1: 2^(q-6) chunks of 64 columns, bit fold_pos(c mod 64)
+  const uint16_t* f2;  // row 2: 2^(q-4) chunks of 16 columns, bit (c mod 4) * 4 + (c / 4 mod 4)
+  const uint32_t* f3;  // row 3: the plain bitmap
+  const uint16_t* l0;  // hot columns of row 0
+};
+
+template <bool kFullFit>
+__device__ __forceinline__ void join_wave_fold(const Dev& d, const uint32_t* __restrict__ tb,
+                                               FoldTables ft, u32x2* __restrict__ stk,
+                                               uint32_t cap, uint32_t n0) {
+  const uint32_t q = d.q, r = d.r;
+  constexpr uint32_t dl = 2u, wmask = 0xFu;
+  const uint32_t lane = lane_id();
+  const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
+  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
+  const uint32_t gsh = q - 8u;  // 2^(q-8) groups of 64 v values per he0
+  const uint32_t n_groups = n0 << gsh;
+  uint32_t g = blockIdx.x * (blockDim.x / kWave) + wib;  // wave w takes groups w, w + W, ...
+  uint32_t size = 0;       // nodes on this wave's stack (uniform)
+  uint32_t nodes = 0;      // stack nodes expanded (uniform)
+  uint32_t resolved = 0;   // row-2 and row-3 tuples resolved by the masks (per lane)
+  uint32_t he0_next = ft.l0[g < n_groups ? g >> gsh : 0u];  // row-0 SRE of the next group
+  for (;;) {
+    if (size >= 64u || (g >= n_groups && size != 0u)) {  // a batch from the top of the stack
+      const uint32_t popped = size < 64u ? size : 64u;
+      nodes += popped;
+      const bool pop = lane < popped;
+      const u32x2 nd = stk[pop ? size - 1u - lane : 0u];
+      const uint32_t x = pop ? nd.x : 0u;
+      const uint32_t he0 = pop ? nd.y & 0xFFFFFFu : 0u;
+      const uint32_t i = pop ? nd.y >> 24 : 2u;
+      const uint32_t top0 = he0 >> (q - dl);
+      const uint32_t sx = (i - 2u) * dl + q;
+      const uint32_t low = ((x >> ((i - 1u) * dl)) ^ he0) & lowmask;
+      uint32_t R = hot_tops(tb, q, dl, wmask, i, low);
+      if (!kFullFit) R &= fit_tops(sx, dl, wmask, top0);
+      R = pop ? R : 0u;
+      if (i + 1u == r) {
+        while (R) {
+          const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+          R &= R - 1u;
+          const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
+          if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
+            const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+            if (pos < d.cand_cap) d.cand[pos] = addr;
+          }
+        }
+      }
+      const uint32_t c = popc32(R);
+      const uint32_t incl = wave_incl_scan(c);
+      const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+      const uint32_t base = size - popped;
+      if (base + total <= cap) {
+        uint32_t pos = base + total - (incl - c);
+        const uint32_t meta = he0 | ((i + 1u) << 24);
+        while (R) {
+          const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
+          R &= R - 1u;
+          const u32x2 child = {kFullFit || sx < 32u ? x | (t << sx) : x, meta};
+          if (--pos < cap) stk[pos] = child;
+        }
+        size = base + total;
+      } else {
+        const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+        nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
+        size = base;
+      }
+    } else if (g < n_groups) {  // 64 values of v for one he0
+      const uint32_t he0 = __builtin_amdgcn_readfirstlane(he0_next);
+      const uint32_t v = ((g & ((1u << gsh) - 1u)) << 6) | lane;
+      g += n_waves;
+      he0_next = ft.l0[g < n_groups ? g >> gsh : 0u];
+      const uint32_t e = he0 & 63u;
+      const uint32_t c2 = (he0 ^ (he0 >> 2)) & 15u;  // row 2: column offset j'/4 ^ c2
+      const uint32_t c3 = (he0 ^ (he0 >> 4)) & 3u;   // row 3: column offset j'/16 ^ c3
+      const u32x2 m1 = ft.f1[((he0 >> 6) ^ v) & (qmask >> 6)];
+      const uint32_t p2 = xor_perm16(ft.f2[((he0 >> 4) ^ v) & (qmask >> 4)],
+                                     ((c2 & 3u) << 2) | (c2 >> 2));
+      const uint32_t i3 = ((he0 >> 2) ^ v) & lowmask;
+      uint32_t n3 = (ft.f3[i3 >> 3] >> ((i3 & 7u) << 2)) & 15u;
+      if (c3 & 1u) n3 = ((n3 >> 1) & 5u) | ((n3 & 5u) << 1);
+      if (c3 & 2u) n3 = ((n3 >> 2) & 3u) | ((n3 & 3u) << 2);
+      const uint32_t r2 = p2 | (p2 << 16);
+      uint32_t r3 = n3 | (n3 << 4);
+      r3 |= r3 << 8;
+      r3 |= r3 << 16;
+      uint32_t mlo = m1.x & r2 & r3, mhi = m1.y & r2 & r3;
+      const uint32_t n_j = popc32(mlo) + popc32(mhi);  // row-3 tuples of (he0, v)
+      resolved += n_j;
+      if (v < (1u << (q - 4u))) resolved += popc32(m1.x & r2) + popc32(m1.y & r2);  // row 2
+      const uint32_t top0 = he0 >> (q - dl);
+      const uint32_t m4 = hot_tops(tb, q, dl, wmask, 4u, (v ^ he0) & lowmask);
+      const uint32_t c = n_j * popc32(m4);  // row-4 tuples: nodes of row 5
+      const uint32_t incl = wave_incl_scan(c);
+      const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+      uint64_t M = m4 ? ((uint64_t)mhi << 32) | mlo : 0ull;  // prefixes with children
+      const uint32_t xv = v << 6;
+      const uint32_t tsh = q + 4u;  // first bit of the row-4 extension (q + 6 <= 32)
+      if (size + total <= cap) {  // uniform
+        uint32_t pos = size + total - (incl - c);  // this lane's children end here
+        const uint32_t meta = he0 | (5u << 24);
+        while (M) {
+          const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(M)) ^ e);
+          M &= M - 1ull;
+#pragma unroll
+          for (uint32_t u = 0; u < 4u; ++u)
+            if ((m4 >> u) & 1u) {  // positions stay in [size, size + total)
+              const u32x2 child = {xj | ((u ^ top0) << tsh), meta};
+              stk[--pos] = child;
+            }
+        }
+        size += total;
+      } else {  // no room: each lane searches its children's subtrees itself
+        const uint32_t sx5 = 3u * dl + q;
+        uint32_t e_sub = 0;
+        while (M) {
+          const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(M)) ^ e);
+          M &= M - 1ull;
+          uint32_t R = m4;
+          while (R) {
+            const uint32_t x5 = xj | (((uint32_t)__builtin_ctz(R) ^ top0) << tsh);
+            R &= R - 1u;
+            const uint32_t low5 = ((x5 >> (4u * dl)) ^ he0) & lowmask;
+            uint32_t R5 = hot_tops(tb, q, dl, wmask, 5u, low5);
+            if (!kFullFit) R5 &= fit_tops(sx5, dl, wmask, top0);
+            e_sub += 1u + join_lane_dfs(d, tb, wmask, lowmask, qmask, x5, he0, 5u, R5);
+          }
+        }
+        nodes += __builtin_amdgcn_readfirstlane(wave_sum(e_sub));
+      }
+    } else {
+      break;
+    }
+  }
+  resolved = wave_sum(resolved);
+  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes + resolved);
+}
+
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
 template <bool kTbLds>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
@@ -714,6 +882,45 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
   const bool small = (uint64_t)n0 * n1 <= 0xFFFFFFFFull && n0 < (1u << 24) && n1 < (1u << 24);
   const bool full = (r - 2u) * d.delta + q <= 32u;
+  // rows 1-3 in bulk: delta = 2, rows at least 1/8 hot (row 1 stands for all), the tables
+  // (3 bitmaps of 2^q bits and the row-0 list) fit in the LDS left after the stacks
+  const uint32_t fw = 3u << (q - 5u);  // words of the three reordered bitmaps
+  if (kTbLds && d.delta == 2u && r >= 6u && q >= 8u && q <= 16u && (n1 << 3) >= (1u << q) &&
+      fw + (n0 + 1u) / 2u <= list_words) {
+    u32x2* const f1 = reinterpret_cast<u32x2*>(lw);
+    uint16_t* const f2 = reinterpret_cast<uint16_t*>(lw + (1u << (q - 5u)));
+    uint32_t* const f3 = lw + (2u << (q - 5u));
+    uint16_t* const l0 = reinterpret_cast<uint16_t*>(lw + fw);
+    const uint32_t* const h = d.hot + (1u << (q - 5u));  // row 1 of the plain bitmap
+    for (uint32_t c = threadIdx.x; c < (1u << (q - 6u)); c += blockDim.x) {
+      const uint32_t w0 = h[2u * c], w1 = h[2u * c + 1u];
+      u32x2 o = {0u, 0u};
+      for (uint32_t j = 0; j < 64u; ++j) {
+        const uint32_t bit = ((j < 32u ? w0 : w1) >> (j & 31u)) & 1u;
+        const uint32_t p = fold_pos(j);
+        if (p < 32u) o.x |= bit << p; else o.y |= bit << (p - 32u);
+      }
+      f1[c] = o;
+    }
+    for (uint32_t c = threadIdx.x; c < (1u << (q - 4u)); c += blockDim.x) {
+      const uint32_t w = (h[(1u << (q - 5u)) + (c >> 1)] >> ((c & 1u) << 4)) & 0xFFFFu;
+      uint32_t o = 0;
+      for (uint32_t j = 0; j < 16u; ++j) o |= ((w >> j) & 1u) << (((j & 3u) << 2) | (j >> 2));
+      f2[c] = (uint16_t)o;
+    }
+    for (uint32_t w = threadIdx.x; w < (1u << (q - 5u)); w += blockDim.x)
+      f3[w] = h[(2u << (q - 5u)) + w];
+    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) l0[j] = (uint16_t)g0[j];
+    if (blockIdx.x == 0 && threadIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
+      atomicAdd(&d.ctrl->join_nodes, (unsigned long long)n0 * n1);
+    __syncthreads();
+    const FoldTables ft{f1, f2, f3, l0};
+    if (full)
+      join_wave_fold<true>(d, tb, ft, stk, cap, n0);
+    else
+      join_wave_fold<false>(d, tb, ft, stk, cap, n0);
+    return;
+  }
   auto run = [&](auto lists) {
     if (small && full)
       join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);

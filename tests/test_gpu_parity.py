@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from gpu_util import (assert_estimates_close, assert_scan_equal, assert_state_equal,
-                      dev_pkts, gpu_candidates)
+                      dev_pkts, gpu_candidates, gpu_hot)
 from paper_1805_09246_amd import sps
 
 pytestmark = pytest.mark.gpu
@@ -285,3 +285,61 @@ def test_join_dense_rows_stack_fallback():
     o.ingest(p, 1)
     assert_scan_equal(g, o, 1, 64.0, "dense rows")
     assert len(gpu_candidates(g)) > 10000
+
+
+def _dense_sketch(params, n_pkts, n_hosts, seed):
+    """Random peers towards few hosts: about a quarter to a half of every SRE row hot."""
+    rng = np.random.default_rng(seed)
+    hosts = rng.integers(0, 1 << 32, n_hosts, dtype=np.uint64).astype(np.uint32)
+    p = rng.integers(0, 1 << 32, size=(n_pkts, 2), dtype=np.uint64).astype(np.uint32)
+    p[:, 1] = hosts[rng.integers(0, n_hosts, n_pkts)]
+    g, o = sps.Sketch(params), oracle.OracleSketch(params)
+    g.ingest(dev_pkts(p), 1)
+    o.ingest(p, 1)
+    return g, o
+
+
+def _join_nodes(g, k, threshold, cap=1 << 18):
+    d_out = torch.empty(cap * 24, dtype=torch.uint8, device="cuda")
+    d_info = torch.zeros(sps.INFO_WORDS, dtype=torch.int32, device="cuda")
+    sps.sps_scan_async(g.h, k, threshold, d_out, cap, d_info)
+    torch.cuda.synchronize()
+    inf = d_info.cpu().numpy().view(np.uint32)
+    return int(inf[sps.INFO_NODES_LO]) | (int(inf[sps.INFO_NODES_HI]) << 32)
+
+
+DENSE_D2 = [  # delta = 2, rows dense enough that rows 1-3 are searched in bulk
+    (dict(q=8, r=14), 4000, 300),    # a quarter hot, coverage exactly 32 bits
+    (dict(q=8, r=15), 4000, 300),    # 34 bits: the top row's extensions must stay below 2^32
+    (dict(q=10, r=13), 10000, 1000), # 15 % hot
+    (dict(q=8, r=14), 6000, 300),    # 43 % hot: batches outgrow the stack, per-lane search
+]
+
+
+@pytest.mark.parametrize("shape,n_pkts,n_hosts", DENSE_D2,
+                         ids=[f"q{s['q']}r{s['r']}n{n}" for s, n, _ in DENSE_D2])
+def test_join_dense_delta2(shape, n_pkts, n_hosts):
+    """Dense rows at delta = 2: candidates, results and the number of search-tree nodes the
+    join expanded (Alg. 4-5 tuples grown through rows 1 .. r-2) match the oracle."""
+    params = dict(shape, delta=2, eta=8, qp=8, rp=2, etap=64, deltap=64, theta=64,
+                  anet_side=0, seed=1)
+    g, o = _dense_sketch(params, n_pkts, n_hosts, seed=1)
+    assert_scan_equal(g, o, 1, 64.0, f"dense delta 2 {shape}")
+    assert gpu_hot(g)[1].sum() * 8 >= (1 << shape["q"])  # dense enough for the bulk rows
+    _, levels = o.join_tuples(o.hot(1), levels=True)
+    assert _join_nodes(g, 1, 64.0) == int(levels[1:shape["r"] - 1].sum())
+    g.close()
+
+
+@pytest.mark.parametrize("shape", [dict(SMALL), dict(SMALL, q=14, r=11, delta=2, qp=10, rp=8)],
+                         ids=["small", "c2shape"])
+def test_join_node_count_sparse(shape):
+    """Sparse rows (the ordinary search): the expanded-node count is the oracle's tuple count."""
+    rng = np.random.default_rng(3)
+    g, o = sps.Sketch(shape), oracle.OracleSketch(shape)
+    p = _rand_pkts(rng, 60000)
+    g.ingest(dev_pkts(p), 1)
+    o.ingest(p, 1)
+    _, levels = o.join_tuples(o.hot(1), levels=True)
+    assert _join_nodes(g, 1, 64.0) == int(levels[1:shape["r"] - 1].sum())
+    g.close()

@@ -183,6 +183,36 @@ def test_join_empty_and_full_rows():
     assert all(sk.hash(sk.RHFG, 0, int(x)) == 17 for x in got[::4096])
 
 
+@pytest.mark.parametrize("shape", [dict(q=6, r=15, delta=2), dict(q=8, r=10, delta=3)])
+def test_join_tuple_levels_count_prefixes(shape):
+    """The tuples grown through row i are the pairs (he0, x) of a hot row-0 column and an
+    address prefix of (i - 1) delta + q bits whose windows B(1..i) (Eq. 7) land on hot columns
+    he0 ^ B(j) of rows 1..i.  Counted here by enumerating every prefix, for the rows whose
+    prefixes have at most 20 bits, on dense random rows."""
+    q, r, d = shape["q"], shape["r"], shape["delta"]
+    params = dict(shape, eta=8, qp=4, rp=1, etap=16, deltap=16, theta=1024, anet_side=0, seed=9)
+    sk = oracle.OracleSketch(params)
+    rng = np.random.default_rng(q * 7 + r)
+    hot = (rng.random((r, 1 << q)) < 0.3).astype(np.uint8)
+    _, levels = sk.join_tuples(hot, levels=True)
+    he0 = np.nonzero(hot[0])[0].astype(np.int64)
+    qm = (1 << q) - 1
+    checked = 0
+    for i in range(1, r):
+        bits = (i - 1) * d + q
+        if bits > 20:
+            break
+        x = np.arange(1 << bits, dtype=np.int64)
+        ok = np.ones((len(he0), len(x)), dtype=bool)
+        for j in range(1, i + 1):
+            win = (x >> ((j - 1) * d)) & qm
+            ok &= hot[j][he0[:, None] ^ win[None, :]].astype(bool)
+        assert int(levels[i]) == int(ok.sum()), f"row {i}"
+        checked += 1
+    assert checked >= 3
+    assert levels[1] == hot[0].sum() * hot[1].sum()
+
+
 # ---------------------------------------------------------------- estimator laws
 def _surjections(alpha, eta):
     """Lemma (Sec. 3.2, full version): FN(alpha, eta) = eta^alpha - sum_{i<eta} C(eta,i) FN(alpha,i),
