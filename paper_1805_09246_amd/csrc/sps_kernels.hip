@@ -700,12 +700,15 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
 // p = (j' mod 4) * 16 + (j' / 4 mod 4) * 4 + j' / 16), makes row 1's part a plain 64-bit
 // word of a reordered copy of its bitmap, row 2's part a 16-bit pattern repeated 4 times and
 // row 3's a 4-bit pattern repeated 16 times; both patterns only need a XOR permutation of
-// bit positions that is the same for the whole wave (he0 is uniform).  The mask's prefixes
-// are exactly the search's row-3 tuples; one transposed-table entry of row 4 then gives
-// their 2^delta extensions, and the resulting row-4 tuples go on the stack as nodes of
-// row 5 for the ordinary search.  Every v is visited (2^(q-2) per he0), so this pays off
-// only when rows are dense; the caller decides.  The tuples of rows 1-3 that the masks
-// resolve are counted, so the node count is the same as the ordinary search's.
+// bit positions that is the same for the whole wave (he0 is uniform).  Rows 1 and 2 only
+// see w = v mod 2^(q-4), so a lane takes one w and its four v = w + k 2^(q-4): one row-1
+// and one row-2 chunk serve all four, and reordered copies of rows 3 and 4 hold the four
+// row-3 patterns and the four row-4 extension sets in one 16-bit entry each.  The mask's
+// prefixes are exactly the search's row-3 tuples; the row-4 entry gives their 2^delta
+// extensions, and the resulting row-4 tuples go on the stack as nodes of row 5 for the
+// ordinary search.  Every v is visited (2^(q-2) per he0), so this pays off only when rows
+// are dense; the caller decides.  The row-2 and row-3 tuples the masks resolve are
+// counted, so the node count is the same as the ordinary search's.
 __device__ __forceinline__ uint32_t xor_perm16(uint32_t x, uint32_t c) {  // bit y <- bit y ^ c
   if (c & 1u) x = ((x >> 1) & 0x5555u) | ((x & 0x5555u) << 1);
   if (c & 2u) x = ((x >> 2) & 0x3333u) | ((x & 0x3333u) << 2);
@@ -719,10 +722,14 @@ __host__ __device__ __forceinline__ uint32_t fold_pos(uint32_t j) {
   return ((j & 3u) << 4) | (j & 12u) | (j >> 4);
 }
 
+// Reordered bitmaps of rows 1-4; for rows 3 and 4, L is the low q - 4 bits of the column
+// index (row 3: of the column / 4; row 4: of the column's low q - 2 bits) and T the two bits
+// above them, so that the four values of T sit in one 16-bit entry.
 struct FoldTables {
   const u32x2* f1;     // row 1: 2^(q-6) chunks of 64 columns, bit fold_pos(c mod 64)
   const uint16_t* f2;  // row 2: 2^(q-4) chunks of 16 columns, bit (c mod 4) * 4 + (c / 4 mod 4)
-  const uint32_t* f3;  // row 3: the plain bitmap
+  const uint16_t* f3;  // row 3: entry L, bit 4T + b = column 4 (L + T 2^(q-4)) + b
+  const uint16_t* f4;  // row 4: entry L, bit 4T + u = column L + T 2^(q-4) + u 2^(q-2)
   const uint16_t* l0;  // hot columns of row 0
 };
 
@@ -736,7 +743,7 @@ __device__ __forceinline__ void join_wave_fold(const Dev& d, const uint32_t* __r
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
   const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
-  const uint32_t gsh = q - 8u;  // 2^(q-8) groups of 64 v values per he0
+  const uint32_t gsh = q - 10u;  // 2^(q-10) groups of 64 w values per he0
   const uint32_t n_groups = n0 << gsh;
   uint32_t g = blockIdx.x * (blockDim.x / kWave) + wib;  // wave w takes groups w, w + W, ...
   uint32_t size = 0;       // nodes on this wave's stack (uniform)
@@ -788,65 +795,80 @@ __device__ __forceinline__ void join_wave_fold(const Dev& d, const uint32_t* __r
         nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
         size = base;
       }
-    } else if (g < n_groups) {  // 64 values of v for one he0
+    } else if (g < n_groups) {  // 64 values of w for one he0, each with its 4 values of v
       const uint32_t he0 = __builtin_amdgcn_readfirstlane(he0_next);
-      const uint32_t v = ((g & ((1u << gsh) - 1u)) << 6) | lane;
+      const uint32_t w = ((g & ((1u << gsh) - 1u)) << 6) | lane;  // w < 2^(q-4)
       g += n_waves;
       he0_next = ft.l0[g < n_groups ? g >> gsh : 0u];
-      const uint32_t e = he0 & 63u;
+      const uint32_t e = he0 & 63u, top0 = he0 >> (q - dl);
       const uint32_t c2 = (he0 ^ (he0 >> 2)) & 15u;  // row 2: column offset j'/4 ^ c2
       const uint32_t c3 = (he0 ^ (he0 >> 4)) & 3u;   // row 3: column offset j'/16 ^ c3
-      const u32x2 m1 = ft.f1[((he0 >> 6) ^ v) & (qmask >> 6)];
-      const uint32_t p2 = xor_perm16(ft.f2[((he0 >> 4) ^ v) & (qmask >> 4)],
-                                     ((c2 & 3u) << 2) | (c2 >> 2));
-      const uint32_t i3 = ((he0 >> 2) ^ v) & lowmask;
-      uint32_t n3 = (ft.f3[i3 >> 3] >> ((i3 & 7u) << 2)) & 15u;
-      if (c3 & 1u) n3 = ((n3 >> 1) & 5u) | ((n3 & 5u) << 1);
-      if (c3 & 2u) n3 = ((n3 >> 2) & 3u) | ((n3 & 3u) << 2);
+      const uint32_t wm = (1u << (q - 4u)) - 1u;
+      const u32x2 m1 = ft.f1[((he0 >> 6) ^ w) & (qmask >> 6)];
+      const uint32_t p2 = xor_perm16(ft.f2[((he0 >> 4) ^ w) & wm], ((c2 & 3u) << 2) | (c2 >> 2));
+      // row 3 and row 4 for v = w + k 2^(q-4), k = 0..3: nibble k of each, after the shuffle
+      const uint32_t n3s = xor_perm16(ft.f3[((he0 >> 2) ^ w) & wm], c3 | (top0 << 2));
+      const uint32_t m4s = xor_perm16(ft.f4[(he0 ^ w) & wm], ((he0 >> (q - 4u)) & 3u) << 2);
       const uint32_t r2 = p2 | (p2 << 16);
-      uint32_t r3 = n3 | (n3 << 4);
-      r3 |= r3 << 8;
-      r3 |= r3 << 16;
-      uint32_t mlo = m1.x & r2 & r3, mhi = m1.y & r2 & r3;
-      const uint32_t n_j = popc32(mlo) + popc32(mhi);  // row-3 tuples of (he0, v)
-      resolved += n_j;
-      if (v < (1u << (q - 4u))) resolved += popc32(m1.x & r2) + popc32(m1.y & r2);  // row 2
-      const uint32_t top0 = he0 >> (q - dl);
-      const uint32_t m4 = hot_tops(tb, q, dl, wmask, 4u, (v ^ he0) & lowmask);
-      const uint32_t c = n_j * popc32(m4);  // row-4 tuples: nodes of row 5
+      const uint32_t ax = m1.x & r2, ay = m1.y & r2;  // row-2 tuples of (he0, w)
+      resolved += popc32(ax) + popc32(ay);
+      uint64_t M[4];
+      uint32_t c = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < 4u; ++k) {
+        const uint32_t n3 = (n3s >> (4u * k)) & 15u;
+        uint32_t r3 = n3 | (n3 << 4);
+        r3 |= r3 << 8;
+        r3 |= r3 << 16;
+        const uint32_t mx = ax & r3, my = ay & r3;
+        const uint32_t n_j = popc32(mx) + popc32(my);  // row-3 tuples of (he0, v)
+        resolved += n_j;
+        const uint32_t m4 = (m4s >> (4u * k)) & 15u;
+        c += n_j * popc32(m4);  // their row-4 extensions: nodes of row 5
+        M[k] = m4 ? ((uint64_t)my << 32) | mx : 0ull;
+      }
       const uint32_t incl = wave_incl_scan(c);
       const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-      uint64_t M = m4 ? ((uint64_t)mhi << 32) | mlo : 0ull;  // prefixes with children
-      const uint32_t xv = v << 6;
       const uint32_t tsh = q + 4u;  // first bit of the row-4 extension (q + 6 <= 32)
       if (size + total <= cap) {  // uniform
         uint32_t pos = size + total - (incl - c);  // this lane's children end here
         const uint32_t meta = he0 | (5u << 24);
-        while (M) {
-          const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(M)) ^ e);
-          M &= M - 1ull;
 #pragma unroll
-          for (uint32_t u = 0; u < 4u; ++u)
-            if ((m4 >> u) & 1u) {  // positions stay in [size, size + total)
-              const u32x2 child = {xj | ((u ^ top0) << tsh), meta};
-              stk[--pos] = child;
-            }
+        for (uint32_t k = 0; k < 4u; ++k) {
+          const uint32_t m4 = (m4s >> (4u * k)) & 15u;
+          const uint32_t xv = (w | (k << (q - 4u))) << 6;
+          uint64_t Mk = M[k];
+          while (Mk) {
+            const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(Mk)) ^ e);
+            Mk &= Mk - 1ull;
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u)
+              if ((m4 >> u) & 1u) {  // positions stay in [size, size + total)
+                const u32x2 child = {xj | ((u ^ top0) << tsh), meta};
+                stk[--pos] = child;
+              }
+          }
         }
         size += total;
       } else {  // no room: each lane searches its children's subtrees itself
         const uint32_t sx5 = 3u * dl + q;
         uint32_t e_sub = 0;
-        while (M) {
-          const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(M)) ^ e);
-          M &= M - 1ull;
-          uint32_t R = m4;
-          while (R) {
-            const uint32_t x5 = xj | (((uint32_t)__builtin_ctz(R) ^ top0) << tsh);
-            R &= R - 1u;
-            const uint32_t low5 = ((x5 >> (4u * dl)) ^ he0) & lowmask;
-            uint32_t R5 = hot_tops(tb, q, dl, wmask, 5u, low5);
-            if (!kFullFit) R5 &= fit_tops(sx5, dl, wmask, top0);
-            e_sub += 1u + join_lane_dfs(d, tb, wmask, lowmask, qmask, x5, he0, 5u, R5);
+        for (uint32_t k = 0; k < 4u; ++k) {
+          const uint32_t m4 = (m4s >> (4u * k)) & 15u;
+          const uint32_t xv = (w | (k << (q - 4u))) << 6;
+          uint64_t Mk = M[k];
+          while (Mk) {
+            const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(Mk)) ^ e);
+            Mk &= Mk - 1ull;
+            uint32_t R = m4;
+            while (R) {
+              const uint32_t x5 = xj | (((uint32_t)__builtin_ctz(R) ^ top0) << tsh);
+              R &= R - 1u;
+              const uint32_t low5 = ((x5 >> (4u * dl)) ^ he0) & lowmask;
+              uint32_t R5 = hot_tops(tb, q, dl, wmask, 5u, low5);
+              if (!kFullFit) R5 &= fit_tops(sx5, dl, wmask, top0);
+              e_sub += 1u + join_lane_dfs(d, tb, wmask, lowmask, qmask, x5, he0, 5u, R5);
+            }
           }
         }
         nodes += __builtin_amdgcn_readfirstlane(wave_sum(e_sub));
@@ -884,37 +906,45 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   const bool full = (r - 2u) * d.delta + q <= 32u;
   // rows 1-3 in bulk: delta = 2, rows at least 1/8 hot (row 1 stands for all), the tables
   // (3 bitmaps of 2^q bits and the row-0 list) fit in the LDS left after the stacks
-  const uint32_t fw = 3u << (q - 5u);  // words of the three reordered bitmaps
-  if (kTbLds && d.delta == 2u && r >= 6u && q >= 8u && q <= 16u && (n1 << 3) >= (1u << q) &&
+  const uint32_t fw = 4u << (q - 5u);  // words of the four reordered bitmaps
+  if (kTbLds && d.delta == 2u && r >= 6u && q >= 10u && q <= 16u && (n1 << 3) >= (1u << q) &&
       fw + (n0 + 1u) / 2u <= list_words) {
+    const uint32_t rw = 1u << (q - 5u);  // words of one bitmap row
     u32x2* const f1 = reinterpret_cast<u32x2*>(lw);
-    uint16_t* const f2 = reinterpret_cast<uint16_t*>(lw + (1u << (q - 5u)));
-    uint32_t* const f3 = lw + (2u << (q - 5u));
+    uint16_t* const f2 = reinterpret_cast<uint16_t*>(lw + rw);
+    uint16_t* const f3 = reinterpret_cast<uint16_t*>(lw + 2u * rw);
+    uint16_t* const f4 = reinterpret_cast<uint16_t*>(lw + 3u * rw);
     uint16_t* const l0 = reinterpret_cast<uint16_t*>(lw + fw);
-    const uint32_t* const h = d.hot + (1u << (q - 5u));  // row 1 of the plain bitmap
+    const uint32_t* const h = d.hot + rw;  // row 1 of the plain bitmap
+    auto hot_bit = [&](uint32_t row, uint32_t col) {  // row >= 1
+      return (h[(row - 1u) * rw + (col >> 5)] >> (col & 31u)) & 1u;
+    };
     for (uint32_t c = threadIdx.x; c < (1u << (q - 6u)); c += blockDim.x) {
-      const uint32_t w0 = h[2u * c], w1 = h[2u * c + 1u];
       u32x2 o = {0u, 0u};
       for (uint32_t j = 0; j < 64u; ++j) {
-        const uint32_t bit = ((j < 32u ? w0 : w1) >> (j & 31u)) & 1u;
-        const uint32_t p = fold_pos(j);
+        const uint32_t bit = hot_bit(1u, 64u * c + j), p = fold_pos(j);
         if (p < 32u) o.x |= bit << p; else o.y |= bit << (p - 32u);
       }
       f1[c] = o;
     }
-    for (uint32_t c = threadIdx.x; c < (1u << (q - 4u)); c += blockDim.x) {
-      const uint32_t w = (h[(1u << (q - 5u)) + (c >> 1)] >> ((c & 1u) << 4)) & 0xFFFFu;
-      uint32_t o = 0;
-      for (uint32_t j = 0; j < 16u; ++j) o |= ((w >> j) & 1u) << (((j & 3u) << 2) | (j >> 2));
-      f2[c] = (uint16_t)o;
+    const uint32_t wn = 1u << (q - 4u);
+    for (uint32_t c = threadIdx.x; c < wn; c += blockDim.x) {
+      uint32_t o2 = 0, o3 = 0, o4 = 0;
+      for (uint32_t j = 0; j < 16u; ++j) {
+        const uint32_t t = j >> 2, b = j & 3u;  // slot t, bit b
+        o2 |= hot_bit(2u, 16u * c + j) << ((b << 2) | t);
+        o3 |= hot_bit(3u, 4u * (c | (t << (q - 4u))) + b) << j;
+        o4 |= hot_bit(4u, (c | (t << (q - 4u))) | (b << (q - 2u))) << j;
+      }
+      f2[c] = (uint16_t)o2;
+      f3[c] = (uint16_t)o3;
+      f4[c] = (uint16_t)o4;
     }
-    for (uint32_t w = threadIdx.x; w < (1u << (q - 5u)); w += blockDim.x)
-      f3[w] = h[(2u << (q - 5u)) + w];
     for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) l0[j] = (uint16_t)g0[j];
     if (blockIdx.x == 0 && threadIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
       atomicAdd(&d.ctrl->join_nodes, (unsigned long long)n0 * n1);
     __syncthreads();
-    const FoldTables ft{f1, f2, f3, l0};
+    const FoldTables ft{f1, f2, f3, f4, l0};
     if (full)
       join_wave_fold<true>(d, tb, ft, stk, cap, n0);
     else

@@ -309,10 +309,11 @@ def _join_nodes(g, k, threshold, cap=1 << 18):
 
 
 DENSE_D2 = [  # delta = 2, rows dense enough that rows 1-3 are searched in bulk
-    (dict(q=8, r=14), 4000, 300),    # a quarter hot, coverage exactly 32 bits
-    (dict(q=8, r=15), 4000, 300),    # 34 bits: the top row's extensions must stay below 2^32
-    (dict(q=10, r=13), 10000, 1000), # 15 % hot
-    (dict(q=8, r=14), 6000, 300),    # 43 % hot: batches outgrow the stack, per-lane search
+    (dict(q=10, r=13), 15000, 1000),  # a quarter hot, coverage exactly 32 bits
+    (dict(q=10, r=14), 10000, 1000),  # 34 bits: the top row's extensions must stay below 2^32
+    (dict(q=12, r=12), 40000, 4000),  # 15 % hot
+    (dict(q=10, r=13), 20000, 1000),  # a third hot: batches outgrow the stack, per-lane search
+    (dict(q=8, r=14), 4000, 300),     # q < 10: the ordinary search on the same kind of rows
 ]
 
 
