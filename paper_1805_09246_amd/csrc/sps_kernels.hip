@@ -576,7 +576,7 @@ __device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* 
 // kFullFit: every row's extensions stay below bit 32 ((r-2) delta + q <= 32), so the
 // bit-32 limit never removes an extension and extension bits always shift in range.
 template <bool kSmall, bool kFullFit, typename L>
-__device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restrict__ tb,
+__device__ __forceinline__ uint32_t join_wave(const Dev& d, const uint32_t* __restrict__ tb,
                                           u32x2* __restrict__ stk, uint32_t cap, L lists,
                                           uint32_t n0, uint32_t n1) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
@@ -688,7 +688,7 @@ __device__ __forceinline__ void join_wave(const Dev& d, const uint32_t* __restri
       size = base;
     }
   }
-  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes);
+  return nodes;
 }
 
 // The same search with rows 1-3 taken in bulk (delta = 2, dense rows).  For a row-0 SRE he0
@@ -734,7 +734,7 @@ struct FoldTables {
 };
 
 template <bool kFullFit>
-__device__ __forceinline__ void join_wave_fold(const Dev& d, const uint32_t* __restrict__ tb,
+__device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const uint32_t* __restrict__ tb,
                                                FoldTables ft, u32x2* __restrict__ stk,
                                                uint32_t cap, uint32_t n0) {
   const uint32_t q = d.q, r = d.r;
@@ -877,8 +877,7 @@ __device__ __forceinline__ void join_wave_fold(const Dev& d, const uint32_t* __r
       break;
     }
   }
-  resolved = wave_sum(resolved);
-  if (lane == 0) atomicAdd(&d.ctrl->join_nodes, (unsigned long long)nodes + resolved);
+  return nodes + __builtin_amdgcn_readfirstlane(wave_sum(resolved));
 }
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
@@ -906,16 +905,21 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   const bool full = (r - 2u) * d.delta + q <= 32u;
   // rows 1-3 in bulk: delta = 2, rows at least 1/8 hot (row 1 stands for all), the tables
   // (3 bitmaps of 2^q bits and the row-0 list) fit in the LDS left after the stacks
+  uint32_t nodes;                 // nodes this wave expanded
+  unsigned long long extra = 0;   // nodes counted once per grid
   const uint32_t fw = 4u << (q - 5u);  // words of the four reordered bitmaps
   if (kTbLds && d.delta == 2u && r >= 6u && q >= 10u && q <= 16u && (n1 << 3) >= (1u << q) &&
-      fw + (n0 + 1u) / 2u <= list_words) {
+      fw + (n0 + 1u) / 2u <= list_words && fw <= 2u * cap * (blockDim.x / kWave)) {
     const uint32_t rw = 1u << (q - 5u);  // words of one bitmap row
     u32x2* const f1 = reinterpret_cast<u32x2*>(lw);
     uint16_t* const f2 = reinterpret_cast<uint16_t*>(lw + rw);
     uint16_t* const f3 = reinterpret_cast<uint16_t*>(lw + 2u * rw);
     uint16_t* const f4 = reinterpret_cast<uint16_t*>(lw + 3u * rw);
     uint16_t* const l0 = reinterpret_cast<uint16_t*>(lw + fw);
-    const uint32_t* const h = d.hot + rw;  // row 1 of the plain bitmap
+    // rows 1-4 of the plain bitmap, staged where the stacks will be
+    uint32_t* const h = reinterpret_cast<uint32_t*>(sh + off);
+    for (uint32_t j = threadIdx.x; j < fw; j += blockDim.x) h[j] = d.hot[rw + j];
+    __syncthreads();
     auto hot_bit = [&](uint32_t row, uint32_t col) {  // row >= 1
       return (h[(row - 1u) * rw + (col >> 5)] >> (col & 31u)) & 1u;
     };
@@ -941,35 +945,39 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
       f4[c] = (uint16_t)o4;
     }
     for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) l0[j] = (uint16_t)g0[j];
-    if (blockIdx.x == 0 && threadIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
-      atomicAdd(&d.ctrl->join_nodes, (unsigned long long)n0 * n1);
+    if (blockIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
+      extra = (unsigned long long)n0 * n1;
     __syncthreads();
     const FoldTables ft{f1, f2, f3, f4, l0};
-    if (full)
-      join_wave_fold<true>(d, tb, ft, stk, cap, n0);
-    else
-      join_wave_fold<false>(d, tb, ft, stk, cap, n0);
-    return;
-  }
-  auto run = [&](auto lists) {
-    if (small && full)
-      join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);
-    else if (small)
-      join_wave<true, false>(d, tb, stk, cap, lists, n0, n1);
-    else if (full)
-      join_wave<false, true>(d, tb, stk, cap, lists, n0, n1);
-    else
-      join_wave<false, false>(d, tb, stk, cap, lists, n0, n1);
-  };
-  if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
-    uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
-    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
-    for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
-    __syncthreads();
-    run(HotLists<uint16_t>{h, h + n0});
+    nodes = full ? join_wave_fold<true>(d, tb, ft, stk, cap, n0)
+                 : join_wave_fold<false>(d, tb, ft, stk, cap, n0);
   } else {
-    __syncthreads();
-    run(HotLists<uint32_t>{g0, g1});
+    auto run = [&](auto lists) {
+      if (small && full) return join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);
+      if (small) return join_wave<true, false>(d, tb, stk, cap, lists, n0, n1);
+      if (full) return join_wave<false, true>(d, tb, stk, cap, lists, n0, n1);
+      return join_wave<false, false>(d, tb, stk, cap, lists, n0, n1);
+    };
+    if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
+      uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
+      for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
+      for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
+      __syncthreads();
+      nodes = run(HotLists<uint16_t>{h, h + n0});
+    } else {
+      __syncthreads();
+      nodes = run(HotLists<uint32_t>{g0, g1});
+    }
+  }
+  // One counter update per block (thousands of same-address atomics from every wave would
+  // queue behind each other at the end of the kernel): each wave leaves its count in its
+  // own stack, which is empty by now.
+  if ((threadIdx.x & 63u) == 0u) stk[0] = u32x2{nodes, 0u};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const u32x2* const stacks = reinterpret_cast<const u32x2*>(sh + off);
+    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) extra += stacks[(uint64_t)w * cap].x;
+    atomicAdd(&d.ctrl->join_nodes, extra);
   }
 }
 
