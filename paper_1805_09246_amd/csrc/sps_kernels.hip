@@ -485,6 +485,26 @@ __host__ __device__ __forceinline__ uint32_t popc32(uint32_t v) {
 #endif
 }
 
+// Recovered addresses go to a per-block buffer in LDS first and reach the global list with
+// one counter update per block at the end (same-address atomics from every finding lane
+// would otherwise serialise); when the buffer is full they go straight to the global list.
+constexpr uint32_t kCandBuf = 1024;  // entries of the block's candidate buffer
+
+struct CandSink {
+  uint32_t* cnt;  // LDS: addresses offered to the buffer (may pass kCandBuf)
+  uint32_t* buf;  // LDS: kCandBuf entries
+};
+
+__device__ __forceinline__ void put_cand(const Dev& d, const CandSink& cs, uint32_t addr) {
+  const uint32_t k = atomicAdd(cs.cnt, 1u);
+  if (k < kCandBuf) {
+    cs.buf[k] = addr;
+  } else {
+    const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
+    if (pos < d.cand_cap) d.cand[pos] = addr;
+  }
+}
+
 // Stack entries per wave: room for a full batch of children (64 nodes x 2^delta) on top of
 // what the stack usually holds.
 uint32_t join_stack_entries(uint32_t dl) {
@@ -533,8 +553,8 @@ __device__ __forceinline__ void pair_coords(uint64_t p, uint32_t n1, double rcp,
 // extensions (over u = t ^ top0) are R; every descendant is visited once, depth first:
 // backing up from row i to row i-1 clears row i-1's extension bits from x and recomputes
 // row i-1's extensions above the one just finished.
-__device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* __restrict__ tb,
-                                               uint32_t wmask, uint32_t lowmask, uint32_t qmask,
+__device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const CandSink& cs,
+                                               const uint32_t* __restrict__ tb, uint32_t wmask, uint32_t lowmask, uint32_t qmask,
                                                uint32_t x, uint32_t he0, uint32_t i, uint32_t R) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint32_t top0 = he0 >> (q - dl), dmask = (1u << dl) - 1u;
@@ -558,10 +578,7 @@ __device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* 
     const uint32_t sx = (i - 2u) * dl + q;
     const uint32_t xi = sx < 32u ? x | (t << sx) : x;
     if (i + 1u == r) {
-      if ((fmix32(xi ^ d.seed_rhfg0) & qmask) == he0) {
-        const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-        if (pos < d.cand_cap) d.cand[pos] = xi;
-      }
+      if ((fmix32(xi ^ d.seed_rhfg0) & qmask) == he0) put_cand(d, cs, xi);
     } else {
       x = xi;
       ++i;
@@ -576,7 +593,8 @@ __device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const uint32_t* 
 // kFullFit: every row's extensions stay below bit 32 ((r-2) delta + q <= 32), so the
 // bit-32 limit never removes an extension and extension bits always shift in range.
 template <bool kSmall, bool kFullFit, typename L>
-__device__ __forceinline__ uint32_t join_wave(const Dev& d, const uint32_t* __restrict__ tb,
+__device__ __forceinline__ uint32_t join_wave(const Dev& d, const CandSink& cs,
+                                              const uint32_t* __restrict__ tb,
                                           u32x2* __restrict__ stk, uint32_t cap, L lists,
                                           uint32_t n0, uint32_t n1) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
@@ -661,10 +679,7 @@ __device__ __forceinline__ uint32_t join_wave(const Dev& d, const uint32_t* __re
         const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
         R &= R - 1u;
         const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
-        if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
-          const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-          if (pos < d.cand_cap) d.cand[pos] = addr;
-        }
+        if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) put_cand(d, cs, addr);
       }
     }
     const uint32_t c = popc32(R);  // children to push (0 at the last row)
@@ -683,7 +698,7 @@ __device__ __forceinline__ uint32_t join_wave(const Dev& d, const uint32_t* __re
       }
       size = base + total;
     } else {  // no room: every lane searches its own node's subtree depth first instead
-      const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+      const uint32_t e = join_lane_dfs(d, cs, tb, wmask, lowmask, qmask, x, he0, i, R);
       nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
       size = base;
     }
@@ -734,7 +749,8 @@ struct FoldTables {
 };
 
 template <bool kFullFit>
-__device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const uint32_t* __restrict__ tb,
+__device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink& cs,
+                                                   const uint32_t* __restrict__ tb,
                                                FoldTables ft, u32x2* __restrict__ stk,
                                                uint32_t cap, uint32_t n0) {
   const uint32_t q = d.q, r = d.r;
@@ -770,10 +786,7 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const uint32_t*
           const uint32_t t = (uint32_t)__builtin_ctz(R) ^ top0;
           R &= R - 1u;
           const uint32_t addr = kFullFit || sx < 32u ? x | (t << sx) : x;
-          if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) {
-            const uint32_t pos = atomicAdd(&d.ctrl->n_cand, 1u);
-            if (pos < d.cand_cap) d.cand[pos] = addr;
-          }
+          if ((fmix32(addr ^ d.seed_rhfg0) & qmask) == he0) put_cand(d, cs, addr);
         }
       }
       const uint32_t c = popc32(R);
@@ -791,7 +804,7 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const uint32_t*
         }
         size = base + total;
       } else {
-        const uint32_t e = join_lane_dfs(d, tb, wmask, lowmask, qmask, x, he0, i, R);
+        const uint32_t e = join_lane_dfs(d, cs, tb, wmask, lowmask, qmask, x, he0, i, R);
         nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
         size = base;
       }
@@ -867,7 +880,7 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const uint32_t*
               const uint32_t low5 = ((x5 >> (4u * dl)) ^ he0) & lowmask;
               uint32_t R5 = hot_tops(tb, q, dl, wmask, 5u, low5);
               if (!kFullFit) R5 &= fit_tops(sx5, dl, wmask, top0);
-              e_sub += 1u + join_lane_dfs(d, tb, wmask, lowmask, qmask, x5, he0, 5u, R5);
+              e_sub += 1u + join_lane_dfs(d, cs, tb, wmask, lowmask, qmask, x5, he0, 5u, R5);
             }
           }
         }
@@ -880,7 +893,8 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const uint32_t*
   return nodes + __builtin_amdgcn_readfirstlane(wave_sum(resolved));
 }
 
-// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words].
+// LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words]
+// [candidate buffer: count, base, kCandBuf entries].
 template <bool kTbLds>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                                                           uint32_t list_words) {
@@ -898,6 +912,9 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   }
   u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
   uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
+  uint32_t* const sink = lw + list_words;  // [count, base, kCandBuf entries]
+  const CandSink cs{sink, sink + 2};
+  if (threadIdx.x == 0) sink[0] = 0u;  // visible after the first barrier below
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
   // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
@@ -949,14 +966,14 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
       extra = (unsigned long long)n0 * n1;
     __syncthreads();
     const FoldTables ft{f1, f2, f3, f4, l0};
-    nodes = full ? join_wave_fold<true>(d, tb, ft, stk, cap, n0)
-                 : join_wave_fold<false>(d, tb, ft, stk, cap, n0);
+    nodes = full ? join_wave_fold<true>(d, cs, tb, ft, stk, cap, n0)
+                 : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
   } else {
     auto run = [&](auto lists) {
-      if (small && full) return join_wave<true, true>(d, tb, stk, cap, lists, n0, n1);
-      if (small) return join_wave<true, false>(d, tb, stk, cap, lists, n0, n1);
-      if (full) return join_wave<false, true>(d, tb, stk, cap, lists, n0, n1);
-      return join_wave<false, false>(d, tb, stk, cap, lists, n0, n1);
+      if (small && full) return join_wave<true, true>(d, cs, tb, stk, cap, lists, n0, n1);
+      if (small) return join_wave<true, false>(d, cs, tb, stk, cap, lists, n0, n1);
+      if (full) return join_wave<false, true>(d, cs, tb, stk, cap, lists, n0, n1);
+      return join_wave<false, false>(d, cs, tb, stk, cap, lists, n0, n1);
     };
     if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
       uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
@@ -974,11 +991,17 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   // own stack, which is empty by now.
   if ((threadIdx.x & 63u) == 0u) stk[0] = u32x2{nodes, 0u};
   __syncthreads();
+  const uint32_t nb = sink[0] < kCandBuf ? sink[0] : kCandBuf;  // buffered candidates
   if (threadIdx.x == 0) {
     const u32x2* const stacks = reinterpret_cast<const u32x2*>(sh + off);
     for (uint32_t w = 0; w < blockDim.x / kWave; ++w) extra += stacks[(uint64_t)w * cap].x;
     atomicAdd(&d.ctrl->join_nodes, extra);
+    sink[1] = nb != 0u ? atomicAdd(&d.ctrl->n_cand, nb) : 0u;
   }
+  __syncthreads();
+  const uint32_t base = sink[1];
+  for (uint32_t j = threadIdx.x; j < nb; j += blockDim.x)
+    if (base + j < d.cand_cap) d.cand[base + j] = cs.buf[j];
 }
 
 // Launch shape of the join: one block per compute unit with as many waves (up to 16) as the
@@ -1003,7 +1026,7 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   if (s.waves < 1u) s.waves = 1u;
   s.lds = kLdsBytes;
   s.blocks = (uint32_t)n_cu;
-  s.list_words = (s.lds - fixed - s.waves * stack) / 4u;
+  s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 2u) * 4u) / 4u;
   return s;
 }
 
