@@ -746,6 +746,7 @@ struct FoldTables {
   const uint16_t* f3;  // row 3: entry L, bit 4T + b = column 4 (L + T 2^(q-4)) + b
   const uint16_t* f4;  // row 4: entry L, bit 4T + u = column L + T 2^(q-4) + u 2^(q-2)
   const uint16_t* l0;  // hot columns of row 0
+  uint32_t* next;      // LDS: groups of this block handed out so far
 };
 
 template <bool kFullFit>
@@ -757,17 +758,25 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
   constexpr uint32_t dl = 2u, wmask = 0xFu;
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
-  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t gsh = q - 10u;  // 2^(q-10) groups of 64 w values per he0
-  const uint32_t n_groups = n0 << gsh;
-  uint32_t g = blockIdx.x * (blockDim.x / kWave) + wib;  // wave w takes groups w, w + W, ...
+  // Block b owns a contiguous share of the groups; its waves take them one at a time from a
+  // counter in LDS, so waves that get fewer issue slots simply take fewer groups and all
+  // waves of the block run out of work together.
+  const uint32_t n_all = n0 << gsh;
+  const uint32_t g_end = (uint32_t)((uint64_t)n_all * (blockIdx.x + 1u) / gridDim.x);
+  const uint32_t g_beg = (uint32_t)((uint64_t)n_all * blockIdx.x / gridDim.x);
+  auto take = [&]() -> uint32_t {
+    uint32_t k = 0;
+    if (lane == 0) k = atomicAdd(ft.next, 1u);
+    return g_beg + __builtin_amdgcn_readfirstlane(k);
+  };
+  uint32_t g = take();
   uint32_t size = 0;       // nodes on this wave's stack (uniform)
   uint32_t nodes = 0;      // stack nodes expanded (uniform)
   uint32_t resolved = 0;   // row-2 and row-3 tuples resolved by the masks (per lane)
-  uint32_t he0_next = ft.l0[g < n_groups ? g >> gsh : 0u];  // row-0 SRE of the next group
+  uint32_t he0_next = ft.l0[g < g_end ? g >> gsh : 0u];  // row-0 SRE of the next group
   for (;;) {
-    if (size >= 64u || (g >= n_groups && size != 0u)) {  // a batch from the top of the stack
+    if (size >= 64u || (g >= g_end && size != 0u)) {  // a batch from the top of the stack
       const uint32_t popped = size < 64u ? size : 64u;
       nodes += popped;
       const bool pop = lane < popped;
@@ -808,11 +817,11 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
         nodes += __builtin_amdgcn_readfirstlane(wave_sum(e));
         size = base;
       }
-    } else if (g < n_groups) {  // 64 values of w for one he0, each with its 4 values of v
+    } else if (g < g_end) {  // 64 values of w for one he0, each with its 4 values of v
       const uint32_t he0 = __builtin_amdgcn_readfirstlane(he0_next);
       const uint32_t w = ((g & ((1u << gsh) - 1u)) << 6) | lane;  // w < 2^(q-4)
-      g += n_waves;
-      he0_next = ft.l0[g < n_groups ? g >> gsh : 0u];
+      g = take();
+      he0_next = ft.l0[g < g_end ? g >> gsh : 0u];
       const uint32_t e = he0 & 63u, top0 = he0 >> (q - dl);
       const uint32_t c2 = (he0 ^ (he0 >> 2)) & 15u;  // row 2: column offset j'/4 ^ c2
       const uint32_t c3 = (he0 ^ (he0 >> 4)) & 3u;   // row 3: column offset j'/16 ^ c3
@@ -894,7 +903,7 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
 }
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words]
-// [candidate buffer: count, base, kCandBuf entries].
+// [count, base, next group, -, candidate buffer of kCandBuf entries].
 template <bool kTbLds>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                                                           uint32_t list_words) {
@@ -912,9 +921,9 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   }
   u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
   uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
-  uint32_t* const sink = lw + list_words;  // [count, base, kCandBuf entries]
-  const CandSink cs{sink, sink + 2};
-  if (threadIdx.x == 0) sink[0] = 0u;  // visible after the first barrier below
+  uint32_t* const sink = lw + list_words;  // [count, base, next group, -, kCandBuf entries]
+  const CandSink cs{sink, sink + 4};
+  if (threadIdx.x == 0) sink[0] = sink[2] = 0u;  // visible after the first barrier below
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
   // 32-bit pair arithmetic (24-bit products): pair count and both list sizes small enough
@@ -965,7 +974,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     if (blockIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
       extra = (unsigned long long)n0 * n1;
     __syncthreads();
-    const FoldTables ft{f1, f2, f3, f4, l0};
+    const FoldTables ft{f1, f2, f3, f4, l0, sink + 2};
     nodes = full ? join_wave_fold<true>(d, cs, tb, ft, stk, cap, n0)
                  : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
   } else {
@@ -1026,7 +1035,7 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   if (s.waves < 1u) s.waves = 1u;
   s.lds = kLdsBytes;
   s.blocks = (uint32_t)n_cu;
-  s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 2u) * 4u) / 4u;
+  s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 4u) * 4u) / 4u;
   return s;
 }
 
