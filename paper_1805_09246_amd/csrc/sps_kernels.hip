@@ -759,16 +759,15 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
   const uint32_t lane = lane_id();
   const uint32_t qmask = (1u << q) - 1u, lowmask = (1u << (q - dl)) - 1u;
   const uint32_t gsh = q - 10u;  // 2^(q-10) groups of 64 w values per he0
-  // Block b owns a contiguous share of the groups; its waves take them one at a time from a
-  // counter in LDS, so waves that get fewer issue slots simply take fewer groups and all
-  // waves of the block run out of work together.
-  const uint32_t n_all = n0 << gsh;
-  const uint32_t g_end = (uint32_t)((uint64_t)n_all * (blockIdx.x + 1u) / gridDim.x);
-  const uint32_t g_beg = (uint32_t)((uint64_t)n_all * blockIdx.x / gridDim.x);
+  // Block b owns groups b, b + B, b + 2B, ... (interleaved, so every block sees the same mix
+  // of row-0 SREs); its waves take them one at a time from a counter in LDS, so waves that get
+  // fewer issue slots simply take fewer groups and all waves of the block run out of work
+  // together.
+  const uint32_t g_end = n0 << gsh;
   auto take = [&]() -> uint32_t {
     uint32_t k = 0;
     if (lane == 0) k = atomicAdd(ft.next, 1u);
-    return g_beg + __builtin_amdgcn_readfirstlane(k);
+    return blockIdx.x + __builtin_amdgcn_readfirstlane(k) * gridDim.x;
   };
   uint32_t g = take();
   uint32_t size = 0;       // nodes on this wave's stack (uniform)
