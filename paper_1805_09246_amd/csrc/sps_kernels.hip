@@ -719,11 +719,12 @@ __device__ __forceinline__ uint32_t join_wave(const Dev& d, const CandSink& cs,
 // see w = v mod 2^(q-4), so a lane takes one w and its four v = w + k 2^(q-4): one row-1
 // and one row-2 chunk serve all four, and reordered copies of rows 3 and 4 hold the four
 // row-3 patterns and the four row-4 extension sets in one 16-bit entry each.  The mask's
-// prefixes are exactly the search's row-3 tuples; the row-4 entry gives their 2^delta
-// extensions, and the resulting row-4 tuples go on the stack as nodes of row 5 for the
-// ordinary search.  Every v is visited (2^(q-2) per he0), so this pays off only when rows
-// are dense; the caller decides.  The row-2 and row-3 tuples the masks resolve are
-// counted, so the node count is the same as the ordinary search's.
+// prefixes are exactly the search's row-3 tuples; those whose row-4 entry is not empty go
+// on the stack as nodes of row 4 for the ordinary search (one store each: expanding their
+// extensions here, lane by lane, measured slower).  Every v is visited (2^(q-2) per he0),
+// so this pays off only when rows are dense; the caller decides.  The row-2 and row-3
+// tuples the masks resolve are counted, so the node count is the same as the ordinary
+// search's.
 __device__ __forceinline__ uint32_t xor_perm16(uint32_t x, uint32_t c) {  // bit y <- bit y ^ c
   if (c & 1u) x = ((x >> 1) & 0x5555u) | ((x & 0x5555u) << 1);
   if (c & 2u) x = ((x >> 2) & 0x3333u) | ((x & 0x3333u) << 2);
@@ -833,63 +834,56 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
       const uint32_t r2 = p2 | (p2 << 16);
       const uint32_t ax = m1.x & r2, ay = m1.y & r2;  // row-2 tuples of (he0, w)
       resolved += popc32(ax) + popc32(ay);
-      uint64_t M[4];
+      // Row-3 tuples with at least one row-4 extension go on the stack as nodes of row 4 (they
+      // are counted when expanded); the others are counted here.
+      uint64_t M0, M1, M2, M3;
       uint32_t c = 0;
-#pragma unroll
-      for (uint32_t k = 0; k < 4u; ++k) {
+      auto row3 = [&](uint32_t k, uint64_t& Mk) {
         const uint32_t n3 = (n3s >> (4u * k)) & 15u;
         uint32_t r3 = n3 | (n3 << 4);
         r3 |= r3 << 8;
         r3 |= r3 << 16;
         const uint32_t mx = ax & r3, my = ay & r3;
         const uint32_t n_j = popc32(mx) + popc32(my);  // row-3 tuples of (he0, v)
-        resolved += n_j;
-        const uint32_t m4 = (m4s >> (4u * k)) & 15u;
-        c += n_j * popc32(m4);  // their row-4 extensions: nodes of row 5
-        M[k] = m4 ? ((uint64_t)my << 32) | mx : 0ull;
-      }
+        const bool ext = ((m4s >> (4u * k)) & 15u) != 0u;
+        resolved += ext ? 0u : n_j;
+        c += ext ? n_j : 0u;
+        Mk = ext ? ((uint64_t)my << 32) | mx : 0ull;
+      };
+      row3(0u, M0);
+      row3(1u, M1);
+      row3(2u, M2);
+      row3(3u, M3);
       const uint32_t incl = wave_incl_scan(c);
       const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-      const uint32_t tsh = q + 4u;  // first bit of the row-4 extension (q + 6 <= 32)
       if (size + total <= cap) {  // uniform
-        uint32_t pos = size + total - (incl - c);  // this lane's children end here
-        const uint32_t meta = he0 | (5u << 24);
-#pragma unroll
-        for (uint32_t k = 0; k < 4u; ++k) {
-          const uint32_t m4 = (m4s >> (4u * k)) & 15u;
-          const uint32_t xv = (w | (k << (q - 4u))) << 6;
-          uint64_t Mk = M[k];
-          while (Mk) {
-            const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(Mk)) ^ e);
-            Mk &= Mk - 1ull;
-#pragma unroll
-            for (uint32_t u = 0; u < 4u; ++u)
-              if ((m4 >> u) & 1u) {  // positions stay in [size, size + total)
-                const u32x2 child = {xj | ((u ^ top0) << tsh), meta};
-                stk[--pos] = child;
-              }
-          }
+        uint32_t pos = size + total - (incl - c);  // this lane's nodes end here
+        const uint32_t meta = he0 | (4u << 24);
+        while ((M0 | M1) | (M2 | M3)) {  // lowest k first, one prefix per pass
+          const bool z0 = M0 != 0ull, z1 = M1 != 0ull, z2 = M2 != 0ull;
+          const uint32_t k = z0 ? 0u : (z1 ? 1u : (z2 ? 2u : 3u));
+          const uint64_t Mk = z0 ? M0 : (z1 ? M1 : (z2 ? M2 : M3));
+          const uint32_t p = (uint32_t)__builtin_ctzll(Mk);
+          const uint64_t rest = Mk & (Mk - 1ull);
+          M0 = k == 0u ? rest : M0;
+          M1 = k == 1u ? rest : M1;
+          M2 = k == 2u ? rest : M2;
+          M3 = k == 3u ? rest : M3;
+          const u32x2 node = {((w | (k << (q - 4u))) << 6) | (fold_pos(p) ^ e), meta};
+          stk[--pos] = node;  // positions stay in [size, size + total)
         }
         size += total;
-      } else {  // no room: each lane searches its children's subtrees itself
-        const uint32_t sx5 = 3u * dl + q;
+      } else {  // no room: each lane searches its nodes' subtrees itself
         uint32_t e_sub = 0;
+        uint64_t Ms[4] = {M0, M1, M2, M3};
         for (uint32_t k = 0; k < 4u; ++k) {
           const uint32_t m4 = (m4s >> (4u * k)) & 15u;
           const uint32_t xv = (w | (k << (q - 4u))) << 6;
-          uint64_t Mk = M[k];
+          uint64_t Mk = Ms[k];
           while (Mk) {
-            const uint32_t xj = xv | (fold_pos((uint32_t)__builtin_ctzll(Mk)) ^ e);
+            const uint32_t x4 = xv | (fold_pos((uint32_t)__builtin_ctzll(Mk)) ^ e);
             Mk &= Mk - 1ull;
-            uint32_t R = m4;
-            while (R) {
-              const uint32_t x5 = xj | (((uint32_t)__builtin_ctz(R) ^ top0) << tsh);
-              R &= R - 1u;
-              const uint32_t low5 = ((x5 >> (4u * dl)) ^ he0) & lowmask;
-              uint32_t R5 = hot_tops(tb, q, dl, wmask, 5u, low5);
-              if (!kFullFit) R5 &= fit_tops(sx5, dl, wmask, top0);
-              e_sub += 1u + join_lane_dfs(d, cs, tb, wmask, lowmask, qmask, x5, he0, 5u, R5);
-            }
+            e_sub += 1u + join_lane_dfs(d, cs, tb, wmask, lowmask, qmask, x4, he0, 4u, m4);
           }
         }
         nodes += __builtin_amdgcn_readfirstlane(wave_sum(e_sub));
