@@ -468,12 +468,12 @@ __device__ __forceinline__ uint32_t fit_tops(uint32_t sx, uint32_t dl, uint32_t 
 // lane instead searches its own node's subtree depth first in registers (join_lane_dfs)
 // and nothing is pushed.  Either way every node is expanded exactly once.
 //
-// Pairs are numbered a * n1 + b and cut into groups of 64; wave w of W takes groups w,
-// w + W, w + 2W, ... in order (no shared counter).  Lane j keeps the (a, b) of slot j of the
-// wave's current group; a lane taking a pair reads its coordinates from the owning slot
-// (one cross-lane move), and the next group's are the same advanced by 64 W pairs.  The
-// hot table, the stacks and (when they fit) the two hot lists live in LDS, so the loop
-// touches no global memory except to record a candidate.
+// Pairs are numbered a * n1 + b and cut into groups of 64; block b owns groups b, b + B,
+// b + 2B, ... and its waves take them one at a time from a counter in LDS.  A wave keeps the
+// (a, b) of the first pair of its current and of its next group; a lane's pair follows from
+// them with at most one wrap to the next row (n1 >= 128) or from a corrected
+// double-precision quotient.  The hot table, the stacks and (when they fit) the two hot
+// lists live in LDS, so the loop touches no global memory except to record a candidate.
 constexpr uint32_t kLdsBytes = 160u << 10;  // LDS of one gfx950 compute unit
 constexpr uint32_t kJoinWaves = 16;        // waves per block at most
 
@@ -595,8 +595,8 @@ __device__ __forceinline__ uint32_t join_lane_dfs(const Dev& d, const CandSink& 
 template <bool kSmall, bool kFullFit, typename L>
 __device__ __forceinline__ uint32_t join_wave(const Dev& d, const CandSink& cs,
                                               const uint32_t* __restrict__ tb,
-                                          u32x2* __restrict__ stk, uint32_t cap, L lists,
-                                          uint32_t n0, uint32_t n1) {
+                                              u32x2* __restrict__ stk, uint32_t cap, L lists,
+                                              uint32_t n0, uint32_t n1, uint32_t* next) {
   const uint32_t q = d.q, dl = d.delta, r = d.r;
   const uint64_t pairs = (uint64_t)n0 * n1;
   const uint32_t lane = lane_id();
@@ -604,24 +604,25 @@ __device__ __forceinline__ uint32_t join_wave(const Dev& d, const CandSink& cs,
   const uint32_t wmask = dl == 5u ? 0xFFFFFFFFu : ((1u << (1u << dl)) - 1u);
   const double rcp = 1.0 / (double)n1;
 
-  const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave in block
-  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  const uint64_t stride = 64ull * n_waves;  // pairs between a wave's groups
-  uint64_t g_first = ((uint64_t)blockIdx.x * (blockDim.x / kWave) + wib) * 64ull;
+  // Block b owns the groups b, b + B, b + 2B, ... of 64 pairs; its waves take them one at a
+  // time from a counter in LDS (waves of a block do not progress at equal speed).
+  auto take = [&]() -> uint64_t {
+    uint32_t k = 0;
+    if (lane == 0) k = atomicAdd(next, 1u);
+    const uint64_t g = blockIdx.x + (uint64_t)__builtin_amdgcn_readfirstlane(k) * gridDim.x;
+    return g * 64ull;  // its first pair
+  };
   auto group_n = [pairs](uint64_t first) -> uint32_t {
     return first < pairs ? (pairs - first < 64ull ? (uint32_t)(pairs - first) : 64u) : 0u;
   };
-  uint32_t cur_n = group_n(g_first), nxt_n = group_n(g_first + stride);
+  uint64_t p_cur = take(), p_nxt = take();  // first pairs of the current and the next group
+  uint32_t cur_n = group_n(p_cur), nxt_n = group_n(p_nxt);
   // (a, b) of the first pair of the current and of the next group (uniform); with n1 >= 128 a
   // lane's pair is at most 126 further on, one step past the end of row a at most
   const bool near = n1 >= 128u;
-  const uint32_t step_a = (uint32_t)(stride / n1), step_b = (uint32_t)(stride % n1);
-  uint32_t ca = (uint32_t)(g_first / n1), cb = (uint32_t)(g_first % n1);
-  uint32_t na = ca + step_a, nb = cb + step_b;
-  if (nb >= n1) {
-    nb -= n1;
-    ++na;
-  }
+  uint32_t ca, cb, na, nb;
+  pair_coords<false>(p_cur, n1, rcp, ca, cb);
+  pair_coords<false>(p_nxt, n1, rcp, na, nb);
   uint32_t used = 0;  // pairs of the current group already taken (uniform)
   uint32_t size = 0;  // nodes on this wave's stack (uniform)
   uint32_t nodes = 0;  // nodes this wave expanded (uniform; at most a few times 10^5)
@@ -646,7 +647,7 @@ __device__ __forceinline__ uint32_t join_wave(const Dev& d, const CandSink& cs,
       a = wrap ? a + 1u : a;
       b = wrap ? b - n1 : b;
     } else {
-      pair_coords<kSmall>(g_first + (k < t1 ? used + k : stride + (k - t1)), n1, rcp, a, b);
+      pair_coords<kSmall>(k < t1 ? p_cur + used + k : p_nxt + (k - t1), n1, rcp, a, b);
     }
     const uint32_t phe0 = lists.he0(fresh ? a : 0u), phe1 = lists.he1(fresh ? b : 0u);
     const uint32_t x = pop ? nd.x : (fresh ? phe0 ^ phe1 : 0u);
@@ -660,18 +661,14 @@ __device__ __forceinline__ uint32_t join_wave(const Dev& d, const CandSink& cs,
     R = pop || fresh ? R : 0u;
     used += t1;
     if (used == cur_n && nxt_n != 0u) {  // move on to the next group
-      g_first += stride;
+      p_cur = p_nxt;
       cur_n = nxt_n;
-      nxt_n = group_n(g_first + stride);
       used = t2;
       ca = na;
       cb = nb;
-      na += step_a;
-      nb += step_b;
-      if (nb >= n1) {
-        nb -= n1;
-        ++na;
-      }
+      p_nxt = take();
+      nxt_n = group_n(p_nxt);
+      pair_coords<false>(p_nxt, n1, rcp, na, nb);
     }
     const bool last = i + 1u == r;
     if (last) {
@@ -972,10 +969,10 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                  : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
   } else {
     auto run = [&](auto lists) {
-      if (small && full) return join_wave<true, true>(d, cs, tb, stk, cap, lists, n0, n1);
-      if (small) return join_wave<true, false>(d, cs, tb, stk, cap, lists, n0, n1);
-      if (full) return join_wave<false, true>(d, cs, tb, stk, cap, lists, n0, n1);
-      return join_wave<false, false>(d, cs, tb, stk, cap, lists, n0, n1);
+      if (small && full) return join_wave<true, true>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
+      if (small) return join_wave<true, false>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
+      if (full) return join_wave<false, true>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
+      return join_wave<false, false>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
     };
     if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
       uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
