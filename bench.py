@@ -57,7 +57,7 @@ def stored_traffic(kernel: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(stream, params, window, threshold, n_slices_sample=10, n_scans=2):
+def cpu_baseline(stream, params, window, threshold, n_slices_sample=10, n_scans=10):
     """The oracle timed on the host on a bounded sample: ingest of the first slices, then a
     few scans; scaled to the whole job's packets/s."""
     import oracle
