@@ -892,6 +892,26 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
   return nodes + __builtin_amdgcn_readfirstlane(wave_sum(resolved));
 }
 
+// Block-wide copy from global memory into LDS with eight loads per thread in flight before
+// the first store (a plain strided loop waits out each load's latency in turn).
+template <typename D, typename S>
+__device__ __forceinline__ void copy_to_lds(D* __restrict__ dst, const S* __restrict__ src,
+                                            uint32_t n) {
+  for (uint32_t base = 0; base < n; base += 8u * blockDim.x) {
+    S v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8u; ++u) {
+      const uint32_t i = base + u * blockDim.x + threadIdx.x;
+      v[u] = i < n ? src[i] : S(0);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 8u; ++u) {
+      const uint32_t i = base + u * blockDim.x + threadIdx.x;
+      if (i < n) dst[i] = (D)v[u];
+    }
+  }
+}
+
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words]
 // [count, base, next group, -, candidate buffer of kCandBuf entries].
 template <bool kTbLds>
@@ -905,7 +925,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   uint32_t off = 0;
   if (kTbLds) {
     const uint32_t words = (r << q) >> 5;
-    for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) sh[w] = d.hot_t[w];
+    copy_to_lds(sh, d.hot_t, words);
     tb = sh;
     off = words;  // even: q >= 6
   }
@@ -934,7 +954,8 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     uint16_t* const l0 = reinterpret_cast<uint16_t*>(lw + fw);
     // rows 1-4 of the plain bitmap, staged where the stacks will be
     uint32_t* const h = reinterpret_cast<uint32_t*>(sh + off);
-    for (uint32_t j = threadIdx.x; j < fw; j += blockDim.x) h[j] = d.hot[rw + j];
+    copy_to_lds(h, d.hot + rw, fw);
+    copy_to_lds(l0, g0, n0);
     __syncthreads();
     auto hot_bit = [&](uint32_t row, uint32_t col) {  // row >= 1
       return (h[(row - 1u) * rw + (col >> 5)] >> (col & 31u)) & 1u;
@@ -960,7 +981,6 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
       f3[c] = (uint16_t)o3;
       f4[c] = (uint16_t)o4;
     }
-    for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) l0[j] = (uint16_t)g0[j];
     if (blockIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
       extra = (unsigned long long)n0 * n1;
     __syncthreads();
@@ -976,8 +996,8 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     };
     if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
       uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
-      for (uint32_t j = threadIdx.x; j < n0; j += blockDim.x) h[j] = (uint16_t)g0[j];
-      for (uint32_t j = threadIdx.x; j < n1; j += blockDim.x) h[n0 + j] = (uint16_t)g1[j];
+      copy_to_lds(h, g0, n0);
+      copy_to_lds(h + n0, g1, n1);
       __syncthreads();
       nodes = run(HotLists<uint16_t>{h, h + n0});
     } else {
