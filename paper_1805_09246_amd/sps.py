@@ -171,21 +171,38 @@ def sps_reset(h, stream=None):
     _check(lib().sps_reset(h, _stream(stream)), "sps_reset")
 
 
+def _check_pairs(pkts: torch.Tensor, where: str) -> int:
+    """Number of pairs in an (n, 2) tensor of 32-bit (src, dst) values on the device; raises
+    before any launch for any other shape, width or placement."""
+    if not (pkts.dim() == 2 and pkts.shape[1] == 2 and pkts.element_size() == 4):
+        raise ValueError(f"{where}: packets must be an (n, 2) 32-bit tensor, got "
+                         f"{tuple(pkts.shape)} of {pkts.dtype}")
+    n = int(pkts.shape[0])
+    if n and not (pkts.is_cuda and pkts.is_contiguous()):
+        raise ValueError(f"{where}: packets must be a contiguous device tensor")
+    return n
+
+
 def sps_ingest(h, pkts: torch.Tensor, slice_: int, stream=None):
     """pkts: (n, 2) 32-bit device tensor of (src, dst) pairs."""
-    n = pkts.shape[0]
-    assert n == 0 or (pkts.dim() == 2 and pkts.shape[1] == 2 and pkts.element_size() == 4)
+    n = _check_pairs(pkts, "sps_ingest")
     ptr = _dptr(pkts) if n else None
     _check(lib().sps_ingest(h, ptr, n, slice_, _stream(stream)), "sps_ingest")
 
 
-def sps_ingest_batched(hs, pkts_list, slice_: int, stream=None):
+def _batch_arrays(hs, pkts_list, where):
     m = len(hs)
+    if m != len(pkts_list) or m == 0:
+        raise ValueError(f"{where}: {m} sketches for {len(pkts_list)} packet batches")
+    ns = [_check_pairs(p, where) for p in pkts_list]
     harr = (C.c_void_p * m)(*[h.value for h in hs])
-    parr = (C.c_void_p * m)(*[(p.data_ptr() if p.shape[0] else 0) for p in pkts_list])
-    narr = (C.c_size_t * m)(*[p.shape[0] for p in pkts_list])
-    for p in pkts_list:
-        assert p.shape[0] == 0 or (p.is_cuda and p.is_contiguous() and p.element_size() == 4)
+    parr = (C.c_void_p * m)(*[(p.data_ptr() if n else 0) for p, n in zip(pkts_list, ns)])
+    narr = (C.c_size_t * m)(*ns)
+    return m, harr, parr, narr
+
+
+def sps_ingest_batched(hs, pkts_list, slice_: int, stream=None):
+    m, harr, parr, narr = _batch_arrays(hs, pkts_list, "sps_ingest_batched")
     _check(lib().sps_ingest_batched(harr, parr, narr, m, slice_, _stream(stream)),
            "sps_ingest_batched")
 
@@ -377,10 +394,7 @@ def sps_set_tuning(h, blocks_per_cu: int = 0, batch_tile: int = 0):
 
 def sps_autotune_ingest(hs, pkts_list, slice_: int, stream=None):
     """Returns (best tuning dict, list of candidate times in ms)."""
-    m = len(hs)
-    harr = (C.c_void_p * m)(*[h.value for h in hs])
-    parr = (C.c_void_p * m)(*[(p.data_ptr() if p.shape[0] else 0) for p in pkts_list])
-    narr = (C.c_size_t * m)(*[p.shape[0] for p in pkts_list])
+    m, harr, parr, narr = _batch_arrays(hs, pkts_list, "sps_autotune_ingest")
     best = sps_tuning()
     ms = np.zeros(64, dtype=np.float32)
     _check(lib().sps_autotune_ingest(harr, parr, narr, m, slice_, _stream(stream), C.byref(best),

@@ -86,3 +86,26 @@ def test_binding_constants_match_header():
     stages = {k[len("STAGE_"):].lower(): v for k, v in defs.items() if k.startswith("STAGE_")}
     assert stages == {n: j for j, n in enumerate(sps.STAGES)}
     assert defs["NSTAGES"] == len(sps.STAGES)
+
+
+def test_packet_batches_rejected_before_launch():
+    """Every ingest binding refuses a packet tensor that is not (n, 2) x 32 bits on the device
+    before it touches the library: a flat (2n,) tensor would otherwise be read as 2n pairs."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1805_09246_amd import sps
+    h = C.c_void_p(1)  # never dereferenced: the check comes first
+    flat = torch.zeros(20, dtype=torch.int32)
+    wide = torch.zeros((10, 2), dtype=torch.int64)
+    host = torch.zeros((10, 2), dtype=torch.int32)  # right shape, but not device memory
+    for bad in (flat, wide, host):
+        with pytest.raises(ValueError):
+            sps.sps_ingest(h, bad, 1)
+        with pytest.raises(ValueError):
+            sps.sps_ingest_batched([h, h], [torch.zeros((0, 2), dtype=torch.int32), bad], 1)
+        with pytest.raises(ValueError):
+            sps.sps_autotune_ingest([h], [bad], 1)
+    with pytest.raises(ValueError):
+        sps.sps_ingest_batched([h], [host, host], 1)  # one sketch, two batches

@@ -361,6 +361,60 @@ def test_window_equivalence():
         assert np.array_equal(full.row_live(k), win.row_live(k))
 
 
+@pytest.mark.parametrize("deltap", [16, 64])
+def test_features_window_equivalence(deltap):
+    """Per-age features of the learned estimator: x_a after slice cur counts the union-SLE
+    cells of a host that a fresh sketch fed only slices cur-a .. cur has written in every row
+    (Alg. 8 union over the window of the newest a+1 slices), for every a < k.  The fresh
+    sketch's count is taken from its raw cells here, not from the features routine."""
+    params = dict(SMALL, deltap=deltap)
+    sl = _small_stream(6, n_slices=9)
+    cur, k = len(sl), 7
+    full = oracle.OracleSketch(params)
+    for s, p in enumerate(sl, 1):
+        full.ingest(p, s)
+    h = _spec_hashes(params)
+    rng = np.random.default_rng(2)
+    hosts = np.concatenate([np.unique(sl[-1][:, 1])[:40],
+                            rng.integers(0, 1 << 32, 10, dtype=np.uint64).astype(np.uint32)])
+    x = full.features(k, hosts)
+    assert np.all(np.diff(x.astype(np.int64), axis=1) >= 0)  # older ages only add cells
+    for a in range(k):
+        fresh = oracle.OracleSketch(params)
+        for s in range(cur - a, cur + 1):
+            fresh.ingest(sl[s - 1], s)
+        written = fresh.slea() > 0
+        for j, hh in enumerate(hosts.tolist()):
+            m = np.ones(params["etap"], bool)
+            for i in range(params["rp"]):
+                j0 = h["LH"](i, hh) * deltap
+                m &= written[i, j0:j0 + params["etap"]]
+            assert x[j, a] == int(m.sum()), (a, hh)
+
+
+def test_features_from_packets():
+    """The same counts straight from the packets, with no sketch at all: with delta' = eta'
+    (no shared cells) cell z of host x's union SLE is set over a window exactly when, in every
+    row i, some packet of the window has LH_i(aip) = LH_i(x) and H3(bip) = z (Alg. 6, Alg. 8)."""
+    params = dict(SMALL, deltap=64, qp=6)
+    sl = _small_stream(7, n_slices=6, per=400, hosts=60)
+    cur, k = len(sl), 4
+    sk = oracle.OracleSketch(params)
+    for s, p in enumerate(sl, 1):
+        sk.ingest(p, s)
+    h = _spec_hashes(params)
+    hosts = np.unique(np.concatenate(sl)[:, 1])[:25]
+    x = sk.features(k, hosts)
+    for a in range(k):
+        win = np.concatenate(sl[cur - a - 1:])
+        for j, hh in enumerate(hosts.tolist()):
+            sets = []
+            for i in range(params["rp"]):
+                li = h["LH"](i, hh)
+                sets.append({h["H3"](src) for src, dst in win.tolist() if h["LH"](i, dst) == li})
+            assert x[j, a] == len(set.intersection(*sets)), (a, hh)
+
+
 def test_k1_is_discrete_re_le():
     """k = 1 (discrete window): live cells are those set in the current slice alone."""
     sl = _small_stream(2, n_slices=3)
