@@ -10,7 +10,8 @@
  * State representation: every recorder is a u16 *stamp* -- the number of the last slice that
  * wrote it, 0 = never.  The paper's distance recorder (Sec. 3.2) is cur - stamp; a recorder
  * is within a window of k slices ending at the current slice cur exactly when
- * stamp >= max(1, cur - k + 1).  Slices are numbered 1..65534.
+ * stamp >= max(1, cur - k + 1).  Slices are numbered 1..65534; sps_rebase shifts the time
+ * base so a long-running sketch can go on past that.
  *
  * Conventions for every function:
  *   - Returns SPS_OK (0) or a negative SPS_E* code; no exception or abort crosses the ABI.
@@ -174,6 +175,17 @@ int sps_graph_destroy(sps_graph* g);
 /* Time passes with no packets: set the current slice (same rules as sps_ingest). */
 int sps_advance(sps_sketch* s, uint32_t slice);
 
+/* Rebase of the time base (Sec. 3.2: the paper's u16 distance recorders saturate; u16
+ * stamps run out at slice 65534 instead).  Every stamp v of the SRE and SLE arrays becomes
+ * max(v - offset, 0) -- recorders last written at or before slice `offset` read as never
+ * written -- and the current slice becomes cur - offset; later ingests number their slices
+ * in the new base.  Every scan, feature and estimate with a window of at most cur - offset
+ * slices is unchanged; longer windows lose the slices shifted out.  Requires
+ * offset <= cur (else SPS_ESLICE, nothing changed).  Sketches that will be merged must be
+ * rebased by the same offset.  Discrete-mode sketches hold no stamps: only the current
+ * slice moves.  Stream-ordered, one fill-type kernel, capturable. */
+int sps_rebase(sps_sketch* s, uint32_t offset, void* stream);
+
 /* Distributed merge (Alg. 2 and Alg. 7): cell-wise, dst <- max(dst, src[0..nsrc)) over the
  * SRE and SLE arrays (the most recent observation of any router wins), and the current
  * slice becomes the largest of all.  h_src is a host array of nsrc sketches with parameters
@@ -303,7 +315,8 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
 #define SPS_STAGE_PROBE 10
 #define SPS_STAGE_MLP 11
 #define SPS_STAGE_SCAN 12
-#define SPS_NSTAGES 13
+#define SPS_STAGE_REBASE 13
+#define SPS_NSTAGES 14
 int sps_profile_enable(uint32_t stage_mask);
 int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);
 

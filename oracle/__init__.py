@@ -79,6 +79,7 @@ def lib():
         L.or_set_slice.argtypes = [vp, C.c_uint32]
         L.or_ingest.argtypes = [vp, vp, C.c_uint64, C.c_uint32]
         L.or_merge.argtypes = [vp, P(vp), C.c_uint32]
+        L.or_rebase.argtypes = [vp, C.c_uint32]
         L.or_row_live.argtypes = [vp, C.c_uint32, vp]
         L.or_hot.argtypes = [vp, C.c_uint32, vp]
         L.or_join_brute.restype = C.c_int64
@@ -190,6 +191,10 @@ class OracleSketch:
     def merge(self, srcs) -> int:
         arr = (C.c_void_p * len(srcs))(*[s._h.value for s in srcs])
         return int(lib().or_merge(self._h, arr, len(srcs)))
+
+    def rebase(self, offset: int) -> int:
+        """Shift every stamp and the current slice down by offset (0 = never written)."""
+        return int(lib().or_rebase(self._h, offset))
 
     def row_live(self, k: int) -> np.ndarray:
         out = np.zeros(self.params["rp"], dtype=np.uint64)

@@ -311,6 +311,24 @@ int or_merge(or_sketch *dst, or_sketch *const *srcs, uint32_t nsrc) {
 }
 
 /* ------------------------------------------------------------------------------------- */
+/* Rebase of the time base.  The paper's distance recorders (Sec. 3.2) saturate at 65535;  */
+/* u16 stamps run out at slice 65534 instead.  Shifting every stamp down by `offset`      */
+/* (stamps at or below it become 0, never written) and the current slice with them keeps  */
+/* every window of at most cur - offset slices unchanged: a recorder within such a window */
+/* has a stamp above offset before the shift and a positive stamp after it.              */
+/* ------------------------------------------------------------------------------------- */
+
+int or_rebase(or_sketch *s, uint32_t offset) {
+  uint64_t j, n_sre = or_sre_cells(s), n_slea = or_slea_cells(s);
+  if (offset > s->cur) return OR_ESLICE;
+  for (j = 0; j < n_sre; j++) s->sre[j] = s->sre[j] > offset ? (uint16_t)(s->sre[j] - offset) : 0;
+  for (j = 0; j < n_slea; j++)
+    s->slea[j] = s->slea[j] > offset ? (uint16_t)(s->slea[j] - offset) : 0;
+  s->cur -= offset;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------- */
 /* Scan, part 1: k-weights.                                                              */
 /* ------------------------------------------------------------------------------------- */
 

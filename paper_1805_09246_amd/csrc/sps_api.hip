@@ -1,7 +1,7 @@
 // sps_api.hip -- host runtime behind the C ABI of include/sps.h.
 //
 // A sketch is one device block: [scan counters | info words | SRE array | SLE array |
-// hot bitmap | HSE lists | candidates | kept hosts | ordered results].  The SRE and SLE
+// hot bitmap | HSE lists | candidates | kept hosts | ordered results | sort keys].  The SRE and SLE
 // arrays are contiguous, so reset and merge treat them as one flat u16 range.
 #include <hip/hip_runtime.h>
 
@@ -105,7 +105,7 @@ uint64_t splitmix64_next(uint64_t& st) {
 }
 
 struct Layout {
-  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, total;
+  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, skeys, total;
   uint64_t row_len, row_stride, sre_bytes, slea_bytes;
 };
 
@@ -135,6 +135,7 @@ Layout layout_of(const sps_params* p) {
   L.cand = o;   o += round_up(cap * 4, 256);
   L.kept = o;   o += round_up(cap * sizeof(sps_result), 256);
   L.sorted = o; o += round_up(cap * sizeof(sps_result), 256);
+  L.skeys = o;  o += round_up(cap * 8, 256);
   L.total = o;
   return L;
 }
@@ -318,6 +319,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.hse = reinterpret_cast<uint32_t*>(b + L.hse);
   d.cand = reinterpret_cast<uint32_t*>(b + L.cand);
   d.kept = reinterpret_cast<sps_result*>(b + L.kept);
+  d.skeys = reinterpret_cast<uint64_t*>(b + L.skeys);
   s->d_info = reinterpret_cast<uint32_t*>(b + L.info);
   s->d_sorted = reinterpret_cast<sps_result*>(b + L.sorted);
   d.row_len = L.row_len;
@@ -553,6 +555,15 @@ int sps_advance(sps_sketch* s, uint32_t slice) {
   int rc = check_slice(s, slice);
   if (rc) return rc;
   s->cur = slice;
+  return SPS_OK;
+}
+
+int sps_rebase(sps_sketch* s, uint32_t offset, void* stream) {
+  if (!s) return SPS_EINVAL;
+  if (offset > s->cur) return SPS_ESLICE;
+  if (s->p.mode == SPS_MODE_SLIDING)
+    SPS_HIP(sps::launch_rebase(s->state, s->state_bytes, offset, (hipStream_t)stream));
+  s->cur -= offset;
   return SPS_OK;
 }
 

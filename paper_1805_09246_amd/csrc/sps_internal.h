@@ -22,7 +22,8 @@ struct Ctrl {
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
   uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
   unsigned long long join_nodes;  // nodes the candidate search expanded
-  uint32_t pad0[2];
+  uint32_t sort_done;     // blocks of the ordering kernel done with their tiles
+  uint32_t pad0;
   // copies of the last scan's counters, for inspection (not cleared)
   uint32_t last_row_live[kMaxRP];
   uint32_t last_n_cand;
@@ -51,6 +52,7 @@ struct Dev {
   uint32_t* hse;          // [2][2^q] hot-SRE column lists of rows 0 and 1
   uint32_t* cand;         // [cand_cap] recovered candidates
   sps_result* kept;       // [cand_cap] kept hosts, unordered
+  uint64_t* skeys;        // [cand_cap] (host << 32 | index into kept), sorted per 4096-tile
   Ctrl* ctrl;
   uint64_t row_len;       // L' = 2^q' delta' + eta' - delta'
   uint64_t row_stride;    // cells between SLE-array rows (row_len rounded up to 64)
@@ -114,6 +116,7 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
                                  hipStream_t st);
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st);
+hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream_t st);
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
                         uint64_t bytes, bool bits, hipStream_t st);
 hipError_t prepare_join();  // allows the join its LDS (call before the first scan)

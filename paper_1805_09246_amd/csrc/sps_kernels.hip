@@ -224,6 +224,29 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
 }
 
 // ---------------------------------------------------------------------------------------
+// Rebase of the time base: every stamp v becomes max(v - offset, 0), 8 stamps per 16-byte
+// lane access with packed saturating subtracts (padding cells are 0 and stay 0).
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rebase(u16x8* __restrict__ p, uint64_t nvec,
+                                                uint32_t offset) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const u16x8 off = (unsigned short)offset;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+    p[i] = __builtin_elementwise_sub_sat(p[i], off);
+}
+
+hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream_t st) {
+  const uint64_t nvec = bytes / 16;
+  if (nvec == 0 || offset == 0) return hipSuccess;
+  uint64_t blocks = (nvec + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  ProfScope ps(SPS_STAGE_REBASE, st);
+  hipLaunchKernelGGL(k_rebase, dim3((uint32_t)blocks), dim3(256), 0, st,
+                     reinterpret_cast<u16x8*>(p), nvec, offset);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Scan.
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_scan_reset(Ctrl* c, uint32_t* hot_t, uint32_t words) {
@@ -1194,28 +1217,83 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
   return y + b3[0];
 }
 
-// Stage 4: order the kept hosts ascending.  Up to kSortTile hosts: a bitonic sort of (host,
-// index) keys, padded to a power of two with keys above every host (in registers and
-// cross-lane moves up to 1024 hosts, in LDS beyond).  More: a
-// host's rank is the number of smaller kept hosts (hosts are distinct), counted over LDS
-// tiles of the list.  One block; it then writes the info words and the inspection copies
-// and clears the working counters for the next scan (the kernel boundary makes every
-// earlier block's results visible, so no device-wide fence is needed).
+// Stage 4: order the kept hosts ascending (hosts are distinct; keys are host << 32 | index
+// into the unordered kept list, padded with keys above every host).
+//   n <= 1024: block 0 alone, one key per thread, a bitonic network in registers with
+//              cross-lane moves for partners closer than 64 and LDS beyond.
+//   n <= 4096: block 0 alone, a bitonic sort of the whole list in LDS.
+//   n >  4096: every block sorts 4096-key tiles of the list in LDS and writes them to
+//              skeys; the last block to finish (a counter) then places every key at its
+//              rank: its position in its own tile plus, for every other tile, the number of
+//              smaller keys there (a binary search).
+// The block that ends the kernel writes the info words and the inspection copies and clears
+// the working counters for the next scan (kernel boundaries make the earlier kernels'
+// results visible; within this kernel the tiles pass through a release / acquire pair).
 constexpr int kSortThreads = 1024;
 constexpr int kSortTile = 4096;
+
+// Bitonic sort of the first P (a power of two, 64 <= P <= kSortTile) keys in LDS.
+__device__ __forceinline__ void lds_bitonic(uint64_t* key, uint32_t P) {
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const uint64_t a = key[i], b = key[l];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[l] = a;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t pow2_at_least(uint32_t n, uint32_t lo) {
+  uint32_t P = lo;
+  while (P < n) P <<= 1;
+  return P;
+}
+
+// The end of a scan: info words, inspection copies, working counters cleared.
+__device__ void scan_finish(const Dev& d, uint32_t cap, uint32_t* __restrict__ info) {
+  Ctrl* c = d.ctrl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (info) {
+      info[SPS_INFO_KEPT] = c->n_kept;
+      info[SPS_INFO_CAND] = c->n_cand;
+      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
+      info[SPS_INFO_HSE0] = c->hse_count[0];
+      info[SPS_INFO_HSE1] = c->hse_count[1];
+      info[SPS_INFO_NODES_LO] = (uint32_t)c->join_nodes;
+      info[SPS_INFO_NODES_HI] = (uint32_t)(c->join_nodes >> 32);
+      info[7] = 0;
+    }
+    for (uint32_t i = 0; i < (uint32_t)kMaxRP; ++i) c->last_row_live[i] = c->row_live[i];
+    c->last_n_cand = c->n_cand;
+    c->last_hse[0] = c->hse_count[0];
+    c->last_hse[1] = c->hse_count[1];
+  }
+  __syncthreads();
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < kCtrlWorkingWords; i += blockDim.x) w[i] = 0;
+}
 
 __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
                                                             uint32_t cap,
                                                             uint32_t* __restrict__ info) {
   __shared__ uint64_t key[kSortTile];
-  uint32_t* const tile = reinterpret_cast<uint32_t*>(key);
+  __shared__ uint32_t last;
   Ctrl* c = d.ctrl;
   const uint32_t n = min(c->n_kept, d.cand_cap);
+  const bool tiled = out && n > (uint32_t)kSortTile;
+  if (!tiled && blockIdx.x != 0) return;  // block 0 orders short lists alone
   if (out && n <= (uint32_t)kSortThreads) {
-    // one key per thread; partners closer than 64 are in the same wave (cross-lane moves),
-    // farther ones go through LDS
-    uint32_t P = 64;
-    while (P < n) P <<= 1;
+    const uint32_t P = pow2_at_least(n, 64u);
     const uint32_t i = threadIdx.x;
     uint64_t v = i < n ? ((uint64_t)d.kept[i].host << 32) | i : ~0ull;
     for (uint32_t k = 2; k <= P; k <<= 1) {
@@ -1237,67 +1315,51 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
     }
     const uint32_t m = n < cap ? n : cap;
     if (i < m) out[i] = d.kept[(uint32_t)v];
-  } else if (out && n <= (uint32_t)kSortTile) {
-    uint32_t P = 64;
-    while (P < n) P <<= 1;
+  } else if (out && !tiled) {
+    const uint32_t P = pow2_at_least(n, 64u);
     for (uint32_t i = threadIdx.x; i < P; i += blockDim.x)
       key[i] = i < n ? ((uint64_t)d.kept[i].host << 32) | i : ~0ull;
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-          const uint32_t l = i ^ j;
-          if (l > i) {
-            const uint64_t a = key[i], b = key[l];
-            if ((a > b) == ((i & k) == 0)) {
-              key[i] = b;
-              key[l] = a;
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
+    lds_bitonic(key, P);
     const uint32_t m = n < cap ? n : cap;
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
-      out[i] = d.kept[(uint32_t)key[i]];
-  } else if (out) {
-    for (uint32_t base = 0; base < n; base += blockDim.x) {
-      const uint32_t i = base + threadIdx.x;
-      const uint32_t h = i < n ? d.kept[i].host : 0u;
-      uint32_t rank = 0;
-      for (uint32_t t0 = 0; t0 < n; t0 += kSortTile) {
-        __syncthreads();
-        for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile && t0 + j < n; j += blockDim.x)
-          tile[j] = d.kept[t0 + j].host;
-        __syncthreads();
-        const uint32_t m = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
-#pragma unroll 8
-        for (uint32_t j = 0; j < m; ++j) rank += tile[j] < h;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) out[i] = d.kept[(uint32_t)key[i]];
+  } else if (tiled) {
+    const uint32_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+      const uint32_t t0 = t * kSortTile;
+      const uint32_t len = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
+      const uint32_t P = pow2_at_least(len, 64u);
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x)
+        key[i] = i < len ? ((uint64_t)d.kept[t0 + i].host << 32) | (t0 + i) : ~0ull;
+      lds_bitonic(key, P);
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) d.skeys[t0 + i] = key[i];
+      __syncthreads();  // key[] is rewritten by the next tile
+    }
+    // release this block's tiles, then count it; the last block goes on alone
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&c->sort_done, 1u) == gridDim.x - 1u ? 1u : 0u;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // acquire: every block's tiles are visible from here on
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint64_t k = d.skeys[i];
+      const uint32_t own = i / kSortTile;
+      uint32_t rank = i - own * kSortTile;
+      for (uint32_t t = 0; t < n_tiles; ++t) {
+        if (t == own) continue;
+        const uint64_t* tk = d.skeys + (uint64_t)t * kSortTile;
+        uint32_t lo = 0, hi = n - t * kSortTile < (uint32_t)kSortTile ? n - t * kSortTile
+                                                                    : (uint32_t)kSortTile;
+        while (lo < hi) {  // number of keys of tile t below k
+          const uint32_t mid = (lo + hi) >> 1;
+          if (tk[mid] < k) lo = mid + 1u; else hi = mid;
+        }
+        rank += lo;
       }
-      if (i < n && rank < cap) out[rank] = d.kept[i];
+      if (rank < cap) out[rank] = d.kept[(uint32_t)k];
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (info) {
-      info[SPS_INFO_KEPT] = c->n_kept;
-      info[SPS_INFO_CAND] = c->n_cand;
-      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
-      info[SPS_INFO_HSE0] = c->hse_count[0];
-      info[SPS_INFO_HSE1] = c->hse_count[1];
-      info[SPS_INFO_NODES_LO] = (uint32_t)c->join_nodes;
-      info[SPS_INFO_NODES_HI] = (uint32_t)(c->join_nodes >> 32);
-      info[7] = 0;
-    }
-    for (uint32_t i = 0; i < (uint32_t)kMaxRP; ++i) c->last_row_live[i] = c->row_live[i];
-    c->last_n_cand = c->n_cand;
-    c->last_hse[0] = c->hse_count[0];
-    c->last_hse[1] = c->hse_count[1];
-  }
-  __syncthreads();
-  uint32_t* w = reinterpret_cast<uint32_t*>(c);
-  for (uint32_t i = threadIdx.x; i < kCtrlWorkingWords; i += blockDim.x) w[i] = 0;
+  scan_finish(d, cap, info);
 }
 
 // Stage 3 (Alg. 8, Eq. 12, Eq. 9, final filter).  One wave per candidate.  With a host
@@ -1405,7 +1467,9 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   }
   {
     ProfScope ps(SPS_STAGE_SORT, st);
-    hipLaunchKernelGGL(k_rank_sort, dim3(1), dim3(kSortThreads), 0, st, d, out, cap, info);
+    const uint32_t tiles = (d.cand_cap + kSortTile - 1) / kSortTile;
+    const uint32_t blocks = tiles < (uint32_t)n_cu ? tiles : (uint32_t)n_cu;
+    hipLaunchKernelGGL(k_rank_sort, dim3(blocks), dim3(kSortThreads), 0, st, d, out, cap, info);
   }
   return hipGetLastError();
 }

@@ -11,6 +11,10 @@ the time from its arrival to the report of the slice that ingested it.
 Routers are admitted while their sketch fits the device-memory budget; a router that cannot
 be admitted waits (its batches are held) until a resident router leaves and frees a slot.
 Slots are reused: a freed sketch is reset and handed to the next router.
+
+Stamps are u16 slice numbers, so before the internal slice number would pass 65534 every
+resident sketch is rebased (sps_rebase) by the same offset, keeping the newest `window`
+slices; reports keep counting slices from the start of serving.
 """
 from __future__ import annotations
 
@@ -33,6 +37,14 @@ class Report:
     batches: int
     packets: int
     latencies: list            # seconds, one per batch ingested in this slice
+    info_flags: int = 0        # scan info flags: bit 0 candidate list overflowed its capacity,
+                               # bit 1 more hosts kept than the result buffer holds
+    kept: int = 0              # hosts the scan kept (results holds min(kept, result_cap))
+
+    @property
+    def complete(self) -> bool:
+        """False when the scan overflowed a buffer and `results` is truncated."""
+        return self.info_flags == 0
 
 
 class Slot:
@@ -46,7 +58,8 @@ class Server:
     """depth: slices allowed on the GPU at once (results are double-buffered by slice)."""
 
     def __init__(self, params: dict, window: int, threshold: float, budget_bytes: int,
-                 result_cap: int = 4096, use_graph: bool = True, depth: int = 2):
+                 result_cap: int = 4096, use_graph: bool = True, depth: int = 2,
+                 start_slice: int = 0):
         self.params = dict(params)
         self.window = window
         self.threshold = threshold
@@ -68,10 +81,13 @@ class Server:
         self.pending = []                           # (slot, pkts, arrival time)
         self.lock = threading.Lock()
         self.stream = torch.cuda.Stream()
-        self.slice_no = 0
+        self.slice_no = start_slice   # internal slice number (the sketches' time base)
+        self.slice_base = 0            # slices shifted out by rebases
+        self.rebases = 0
         self.inflight = collections.deque()
         self.reports: list[Report] = []
         self.refused = 0
+        self.incomplete = 0        # reports whose scan overflowed a buffer
 
     # ---------------------------------------------------------------- admission
     def used_bytes(self) -> int:
@@ -144,10 +160,13 @@ class Server:
         with self.lock:
             batch, self.pending = self.pending, []
             active = [(s, s.router) for s in self.slots if s.router is not None]
+        st = self.stream
+        if self.slice_no + 1 > sps.SLICE_MAX:
+            self._rebase(self.slice_no - self.window)
         self.slice_no += 1
         s_no = self.slice_no
-        par = s_no % self.depth
-        st = self.stream
+        abs_no = s_no + self.slice_base
+        par = abs_no % self.depth
         with torch.cuda.stream(st):
             for s, _ in active:
                 if s.sketch.cur < s_no:
@@ -173,7 +192,18 @@ class Server:
         per_router = collections.defaultdict(list)
         for slot, p, t in batch:
             per_router[slot.router].append((p.shape[0], t))
-        self.inflight.append((s_no, done, graph, active, per_router))
+        self.inflight.append((abs_no, done, graph, active, per_router))
+
+    def _rebase(self, offset: int):
+        """Shift the time base of every sketch that holds stamps by `offset` (stream-ordered
+        behind the slices already launched).  Reset slots (current slice 0) hold none."""
+        with torch.cuda.stream(self.stream):
+            for slot in self.slots:
+                if slot.sketch.cur >= offset:
+                    slot.sketch.rebase(offset, self.stream)
+        self.slice_no -= offset
+        self.slice_base += offset
+        self.rebases += 1
 
     def collect(self, block: bool = False, limit: int = 1 << 30):
         """Turn finished slices into reports (in slice order)."""
@@ -191,11 +221,15 @@ class Server:
             info = self.info[par].cpu().numpy()
             res = self.res[par].cpu().numpy()
             for slot, router in active:
-                n = int(min(info[slot.index, sps.INFO_KEPT], self.cap))
+                kept = int(info[slot.index, sps.INFO_KEPT])
+                flags = int(info[slot.index, sps.INFO_FLAGS])
+                n = min(kept, self.cap)
                 r = res[slot.index].view(sps.RESULT_DTYPE)[:n].copy()
                 b = per_router.get(router, [])
                 self.reports.append(Report(router, s_no, r, len(b), sum(x[0] for x in b),
-                                           [t_done - t for _, t in b]))
+                                           [t_done - t for _, t in b], flags, kept))
+                if flags:
+                    self.incomplete += 1
 
 
 def poisson_schedule(seed: int, rate_pkts: float, duration_s: float, n_routers: int,

@@ -33,10 +33,11 @@ EXPORTS = [
     "sps_profile_enable", "sps_profile_read", "sps_probe_scatter", "sps_probe_stream",
     "sps_estimate_hosts", "sps_mlp_work_bytes", "sps_mlp_grad", "sps_mlp_adam",
     "sps_mlp_forward", "sps_get_tuning", "sps_set_tuning", "sps_autotune_ingest",
-    "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy",
+    "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy", "sps_rebase",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
-          "estimate", "sort", "features", "probe", "mlp", "scan"]
+          "estimate", "sort", "features", "probe", "mlp", "scan", "rebase"]
+SLICE_MAX = 65534
 
 
 class sps_tuning(C.Structure):
@@ -80,6 +81,7 @@ def lib():
             "sps_ingest": [vp, vp, sz, u32, vp],
             "sps_ingest_batched": [P(vp), P(vp), P(sz), u32, u32, vp],
             "sps_advance": [vp, u32],
+            "sps_rebase": [vp, u32, vp],
             "sps_merge": [vp, P(vp), u32, vp],
             "sps_scan": [vp, u32, C.c_double, vp, sz, P(sz), vp],
             "sps_scan_async": [vp, u32, C.c_double, vp, sz, vp, vp],
@@ -209,6 +211,10 @@ def sps_ingest_batched(hs, pkts_list, slice_: int, stream=None):
 
 def sps_advance(h, slice_: int):
     _check(lib().sps_advance(h, slice_), "sps_advance")
+
+
+def sps_rebase(h, offset: int, stream=None):
+    _check(lib().sps_rebase(h, offset, _stream(stream)), "sps_rebase")
 
 
 def sps_merge(dst, srcs, stream=None):
@@ -451,6 +457,9 @@ class Sketch:
 
     def advance(self, slice_):
         sps_advance(self.h, slice_)
+
+    def rebase(self, offset, stream=None):
+        sps_rebase(self.h, offset, stream)
 
     def merge(self, srcs, stream=None):
         sps_merge(self.h, [s.h for s in srcs], stream)

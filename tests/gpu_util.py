@@ -65,3 +65,25 @@ def assert_scan_equal(g: "sps.Sketch", o, k: int, threshold: float, where=""):
     assert np.array_equal(got["flags"], want["flags"]), f"{where}: flags"
     assert_estimates_close(got["estimate"], want["estimate"], where)
     return got
+
+
+def import_state(g: "sps.Sketch", sre: np.ndarray, slea: np.ndarray, cur: int):
+    """Give a GPU sketch exactly this state (u16 stamps, shapes as in Sketch.state()) through
+    the checkpoint entry points."""
+    if g.cur < cur:
+        g.advance(cur)
+    buf = g.export()
+    body = buf[sps.HEADER_BYTES:].view(np.uint16)
+    body[: sre.size] = sre.ravel()
+    body[sre.size: sre.size + slea.size] = slea.ravel()
+    g.import_(buf)
+    assert g.cur == cur
+
+
+def assert_results_equal(got, want, where=""):
+    """Full result records: hosts, |USLE|^k and flags exact, estimates within ULP_TOL ulp."""
+    assert len(got) == len(want), f"{where}: {len(got)} results, oracle {len(want)}"
+    assert np.array_equal(got["host"], want["host"]), f"{where}: hosts"
+    assert np.array_equal(got["live"], want["live"]), f"{where}: |USLE|^k"
+    assert np.array_equal(got["flags"], want["flags"]), f"{where}: flags"
+    assert_estimates_close(got["estimate"], want["estimate"], where)

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import assert_scan_equal, assert_state_equal, dev_pkts
+from gpu_util import assert_results_equal, assert_scan_equal, assert_state_equal, dev_pkts
 from paper_1805_09246_amd import sps
 from paper_1805_09246_amd.serve import Server
 
@@ -135,7 +135,8 @@ def test_serving_result_same_alone_and_in_mix():
             o.set_slice(k)
         want, _ = o.scan(3, 20.0)
         got = [x for x in mix.reports if x.router == 4 and x.slice == k][0]
-        assert np.array_equal(got.results["host"], want["host"])
+        assert got.complete
+        assert_results_equal(got.results, want, f"served router 4, slice {k}")
 
 
 def test_admission_by_budget_and_slot_reuse():
@@ -157,4 +158,56 @@ def test_admission_by_budget_and_slot_reuse():
     o = oracle.OracleSketch(SMALL)
     o.ingest(held.cpu().numpy().view(np.uint32), 2)
     want, _ = o.scan(3, 20.0)
-    assert np.array_equal(rep[0].results["host"], want["host"])
+    assert_results_equal(rep[0].results, want, "admitted router")
+
+
+def test_serving_flags_truncated_reports():
+    """A scan that keeps more hosts than the serving result buffer, or recovers more
+    candidates than the sketch's candidate capacity, yields a report marked incomplete."""
+    rng = np.random.default_rng(5)
+    many = dev_pkts(_rand_pkts(rng, 200000, hosts=50))
+    srv = Server(SMALL, 3, 1.0, budget_bytes=4 * sps.sps_sketch_bytes(SMALL), result_cap=2)
+    srv.admit(1)
+    srv.submit(1, many)
+    srv.run_slice()
+    srv.collect(block=True)
+    rep = srv.reports[-1]
+    assert rep.kept > 2 and len(rep.results) == 2 and not rep.complete
+    assert rep.info_flags & 2 and srv.incomplete == 1
+    tiny = dict(SMALL, cand_cap=4)
+    srv2 = Server(tiny, 3, 1.0, budget_bytes=4 * sps.sps_sketch_bytes(tiny))
+    srv2.admit(1)
+    srv2.submit(1, many)
+    srv2.run_slice()
+    srv2.collect(block=True)
+    assert srv2.reports[-1].info_flags & 1 and not srv2.reports[-1].complete
+
+
+def test_serving_runs_past_slice_limit():
+    """Serving started near the u16 limit rebases every resident sketch before slice 65535
+    and goes on; every report equals the oracle fed that router's packets from slice 1."""
+    rng = np.random.default_rng(6)
+    routers = [0, 1, 2]
+    srv = Server(SMALL, window=3, threshold=20.0,
+                 budget_bytes=4 * sps.sps_sketch_bytes(SMALL), start_slice=65528)
+    for r in routers:
+        srv.admit(r)
+    sent = {r: [] for r in routers}
+    for k in range(1, 13):
+        for r in routers:
+            p = _rand_pkts(rng, int(rng.integers(500, 20000)))
+            sent[r].append(p)
+            srv.submit(r, dev_pkts(p))
+        srv.run_slice()
+        srv.collect()
+    srv.collect(block=True)
+    assert srv.rebases == 1 and srv.slice_no < 65534
+    for r in routers:
+        o = oracle.OracleSketch(SMALL)
+        reps = sorted((x for x in srv.reports if x.router == r), key=lambda x: x.slice)
+        assert [x.slice for x in reps] == list(range(65529, 65541))
+        for k, (p, rep) in enumerate(zip(sent[r], reps), 1):
+            o.ingest(p, k)
+            want, _ = o.scan(3, 20.0)
+            assert rep.complete
+            assert_results_equal(rep.results, want, f"router {r}, slice {rep.slice}")

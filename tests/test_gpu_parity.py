@@ -344,3 +344,53 @@ def test_join_node_count_sparse(shape):
     _, levels = o.join_tuples(o.hot(1), levels=True)
     assert _join_nodes(g, 1, 64.0) == int(levels[1:shape["r"] - 1].sum())
     g.close()
+
+
+def test_rebase_parity():
+    """The time-base shift (Sec. 3.2 recorders, u16 stamps): state equal to the oracle's after
+    the rebase, scans of windows within the kept slices unchanged, ingest continuing in the
+    new base."""
+    rng = np.random.default_rng(12)
+    g, o = sps.Sketch(SMALL), oracle.OracleSketch(SMALL)
+    for s in range(1, 10):
+        p = _rand_pkts(rng, 20000)
+        g.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+    before = {k: g.scan(k, 30.0) for k in (1, 3)}
+    g.rebase(6)
+    assert o.rebase(6) == 0
+    assert g.cur == 3
+    assert_state_equal(g, o, "rebased")
+    for k in (1, 3):
+        assert np.array_equal(assert_scan_equal(g, o, k, 30.0, f"rebased k={k}"), before[k])
+    p = _rand_pkts(rng, 20000)
+    g.ingest(dev_pkts(p), 4)
+    o.ingest(p, 4)
+    assert_state_equal(g, o, "after the rebase")
+    assert_scan_equal(g, o, 3, 30.0, "after the rebase")
+    with pytest.raises(sps.SpsError) as e:
+        g.rebase(5)
+    assert e.value.code == sps.SPS_ESLICE
+
+
+def test_rebase_crosses_slice_limit():
+    """A sketch driven to slice 65534, refused slice 65535, rebased, and fed on: every scan
+    equals an oracle fed the same packets numbered from slice 1."""
+    rng = np.random.default_rng(13)
+    g = sps.Sketch(SMALL)
+    g.advance(65530)
+    o = oracle.OracleSketch(SMALL)
+    pk = [_rand_pkts(rng, 15000) for _ in range(8)]
+    for j in range(4):                     # slices 65531 .. 65534
+        g.ingest(dev_pkts(pk[j]), 65531 + j)
+        o.ingest(pk[j], j + 1)
+    with pytest.raises(sps.SpsError) as e:
+        g.ingest(dev_pkts(pk[4]), 65535)
+    assert e.value.code == sps.SPS_ESLICE
+    g.rebase(65534 - 4)                    # the newest 4 slices become 1 .. 4
+    assert g.cur == 4
+    assert_state_equal(g, o, "rebased at the limit")
+    for j in range(4, 8):                  # absolute slices 65535 .. 65538
+        g.ingest(dev_pkts(pk[j]), j + 1)
+        o.ingest(pk[j], j + 1)
+        assert_scan_equal(g, o, 3, 30.0, f"absolute slice {65531 + j}")

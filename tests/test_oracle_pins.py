@@ -460,6 +460,49 @@ def test_order_independence():
     assert np.array_equal(a.sre(), b.sre()) and np.array_equal(a.slea(), b.slea())
 
 
+def test_rebase_equals_relabelled_stream():
+    """Rebasing the sketch of slices 1..n by `off` gives exactly the sketch of slices off+1..n
+    alone, relabelled s - off: cells last written at or before slice off read as never
+    written (0), the others keep their age (Sec. 3.2: only the distance matters)."""
+    sl = _small_stream(8, n_slices=9)
+    for off in (0, 3, 8, 9):
+        full = oracle.OracleSketch(SMALL)
+        for s, p in enumerate(sl, 1):
+            full.ingest(p, s)
+        assert full.rebase(off) == 0 and full.cur == 9 - off
+        fresh = oracle.OracleSketch(SMALL)
+        for s in range(off + 1, 10):
+            fresh.ingest(sl[s - 1], s - off)
+        assert np.array_equal(full.sre(), fresh.sre())
+        assert np.array_equal(full.slea(), fresh.slea())
+    assert full.rebase(1) == -2  # below slice 0
+
+
+def test_rebase_keeps_short_windows():
+    """Scans of any window k <= cur - offset give the same hot SREs, row counts, features and
+    report after the rebase; a longer window loses the slices shifted out."""
+    sl = _small_stream(9, n_slices=10)
+    a, b = oracle.OracleSketch(SMALL), oracle.OracleSketch(SMALL)
+    for s, p in enumerate(sl, 1):
+        a.ingest(p, s)
+        b.ingest(p, s)
+    assert b.rebase(6) == 0 and b.cur == 4
+    hosts = np.unique(sl[-1][:, 1])[:30]
+    for k in (1, 2, 4):
+        assert np.array_equal(a.hot(k), b.hot(k))
+        assert np.array_equal(a.row_live(k), b.row_live(k))
+        assert np.array_equal(a.features(k, hosts), b.features(k, hosts))
+        ra, _ = a.scan(k, 20.0)
+        rb, _ = b.scan(k, 20.0)
+        assert np.array_equal(ra, rb)
+    assert (a.row_live(8) > b.row_live(8)).all()
+    # ingest continues in the new time base
+    p = _small_stream(10, n_slices=1)[0]
+    a.ingest(p, 11)
+    b.ingest(p, 5)
+    assert np.array_equal(a.scan(3, 20.0)[0], b.scan(3, 20.0)[0])
+
+
 def test_slice_rules():
     sk = oracle.OracleSketch(SMALL)
     p = _small_stream(5, n_slices=1)[0]
