@@ -255,6 +255,19 @@ int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target
                  const uint32_t* d_idx, size_t n, uint32_t etap, void* d_work, float* d_grad,
                  float* d_loss, void* stream);
 
+/* Allocation-free variant of sps_mlp_grad, for callers that cannot allocate device memory
+ * or pass a workspace (code under stream capture, tight training or serving loops): the
+ * same kernels and the same result, bit for bit, with the per-wave partial gradients kept in
+ * a static device array of the library (about 5 MiB per device, held until the process
+ * exits) instead of d_work.  n <= SPS_MLP_NOALLOC_MAX_N (else SPS_ECAPACITY, nothing
+ * launched).  Calls no allocator.  All calls on one device share that array: calls that
+ * overlap in time on one device (different streams or threads) race and must be serialized
+ * by the caller.  The first call on a device looks up the array's address (synchronous). */
+#define SPS_MLP_NOALLOC_MAX_N 4096
+int sps_mlp_grad_noalloc(const float* d_w, const uint32_t* d_feat, const float* d_target,
+                         const uint32_t* d_idx, size_t n, uint32_t etap, float* d_grad,
+                         float* d_loss, void* stream);
+
 /* One Adam step (Kingma & Ba 2015, bias-corrected; step counts from 1) on d_w with moment
  * buffers d_m, d_v (SPS_MLP_PARAMS floats each). */
 int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32_t step,

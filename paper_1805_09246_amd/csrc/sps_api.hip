@@ -677,6 +677,22 @@ int sps_mlp_grad(const float* d_w, const uint32_t* d_feat, const float* d_target
   return SPS_OK;
 }
 
+int sps_mlp_grad_noalloc(const float* d_w, const uint32_t* d_feat, const float* d_target,
+                         const uint32_t* d_idx, size_t n, uint32_t etap, float* d_grad,
+                         float* d_loss, void* stream) {
+  if (!d_w || !d_feat || !d_target || !d_grad || n == 0 || etap == 0) return SPS_EINVAL;
+  if (n > SPS_MLP_NOALLOC_MAX_N) return SPS_ECAPACITY;
+  float* scratch = nullptr;
+  uint64_t floats = 0;
+  SPS_HIP(sps::mlp_scratch(&scratch, &floats));
+  const uint64_t w = sps::mlp_grad_waves((uint32_t)n);
+  if (w * (SPS_MLP_PARAMS + 1) > floats) return SPS_ECAPACITY;
+  SPS_HIP(sps::launch_mlp_grad(d_w, d_feat, d_target, d_idx, (uint32_t)n, etap, scratch,
+                               scratch + w * SPS_MLP_PARAMS, d_grad, d_loss,
+                               (hipStream_t)stream));
+  return SPS_OK;
+}
+
 int sps_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, uint32_t step,
                  float lr, double beta1, double beta2, float eps, void* stream) {
   if (!d_w || !d_m || !d_v || !d_grad || step == 0) return SPS_EINVAL;

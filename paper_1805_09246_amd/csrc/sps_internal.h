@@ -135,6 +135,9 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
 
 // Learned estimator (sps_mlp.hip).
 uint32_t mlp_grad_waves(uint32_t n);
+// Largest batch of the allocation-free gradient call (its workspace is a static device array).
+constexpr uint32_t kMlpNoAllocMaxN = SPS_MLP_NOALLOC_MAX_N;
+hipError_t mlp_scratch(float** out, uint64_t* floats);
 hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* target,
                            const uint32_t* idx, uint32_t n, uint32_t etap, float* partial,
                            float* partial_loss, float* grad, float* loss, hipStream_t st);

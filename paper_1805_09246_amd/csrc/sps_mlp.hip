@@ -12,6 +12,8 @@
 // fixed order (bitwise reproducible) before Adam.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sps_internal.h"
 
 namespace sps {
@@ -192,6 +194,35 @@ hipError_t launch_mlp_grad(const float* w, const uint32_t* feat, const float* ta
                        partial_loss, waves, 1.f / (float)n, grad, loss);
   }
   return hipGetLastError();
+}
+
+// Workspace of the allocation-free gradient call: the per-wave partial gradients (kP floats
+// per wave) and then the per-wave losses of a batch of at most kMlpNoAllocMaxN samples.  Each
+// device holds its own copy for the life of the process; calls on one device share it.
+constexpr uint32_t kMlpNoAllocWaves = (kMlpNoAllocMaxN + 15) / 16;
+static_assert(kMlpNoAllocWaves % 4 == 0, "whole blocks of four waves");
+static __device__ __align__(256) float scratch[(uint64_t)kMlpNoAllocWaves * (kP + 1)];
+
+// Device address of this device's copy of `scratch`, looked up once per device with that
+// device current (the host-side name of the array is not a device address).
+hipError_t mlp_scratch(float** out, uint64_t* floats) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<float*>(p);
+  }
+  *out = addr[dev];
+  *floats = (uint64_t)kMlpNoAllocWaves * (kP + 1);
+  return hipSuccess;
 }
 
 hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint32_t step,

@@ -22,6 +22,7 @@ F_SATURATED, F_LC_FALLBACK, F_MLP, F_NEAR, F_CLAMPLOW = 1, 2, 4, 8, 16
 INFO_KEPT, INFO_CAND, INFO_FLAGS, INFO_HSE0, INFO_HSE1, INFO_WORDS = 0, 1, 2, 3, 4, 8
 INFO_NODES_LO, INFO_NODES_HI = 5, 6
 MLP_IN, MLP_HIDDEN = 10, 64
+MLP_NOALLOC_MAX_N = 4096
 MLP_PARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 HEADER_BYTES = 64
 
@@ -34,6 +35,7 @@ EXPORTS = [
     "sps_estimate_hosts", "sps_mlp_work_bytes", "sps_mlp_grad", "sps_mlp_adam",
     "sps_mlp_forward", "sps_get_tuning", "sps_set_tuning", "sps_autotune_ingest",
     "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy", "sps_rebase",
+    "sps_mlp_grad_noalloc",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
           "estimate", "sort", "features", "probe", "mlp", "scan", "rebase"]
@@ -90,6 +92,7 @@ def lib():
             "sps_estimate_hosts": [vp, vp, sz, u32, vp, vp],
             "sps_mlp_work_bytes": [sz, P(sz)],
             "sps_mlp_grad": [vp, vp, vp, vp, sz, u32, vp, vp, vp, vp],
+            "sps_mlp_grad_noalloc": [vp, vp, vp, vp, sz, u32, vp, vp, vp],
             "sps_mlp_adam": [vp, vp, vp, vp, u32, C.c_float, C.c_double, C.c_double, C.c_float, vp],
             "sps_mlp_forward": [vp, vp, sz, u32, C.c_int, vp, vp],
             "sps_get_tuning": [vp, P(sps_tuning)],
@@ -288,6 +291,16 @@ def sps_mlp_grad(d_w, d_feat, d_target, d_idx, n: int, etap: int, d_work, d_grad
                               _dptr(d_work), _dptr(d_grad),
                               _dptr(d_loss) if d_loss is not None else None, _stream(stream)),
            "sps_mlp_grad")
+
+
+def sps_mlp_grad_noalloc(d_w, d_feat, d_target, d_idx, n: int, etap: int, d_grad, d_loss=None,
+                         stream=None):
+    _check(lib().sps_mlp_grad_noalloc(_dptr(d_w), _dptr(d_feat), _dptr(d_target),
+                                      _dptr(d_idx) if d_idx is not None else None, n, etap,
+                                      _dptr(d_grad),
+                                      _dptr(d_loss) if d_loss is not None else None,
+                                      _stream(stream)),
+           "sps_mlp_grad_noalloc")
 
 
 def sps_mlp_adam(d_w, d_m, d_v, d_grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
