@@ -568,6 +568,33 @@ def test_exact_truth_bruteforce():
     assert (fpr, fnr, tfr) == (0.25, 0.5, 0.75)
 
 
+def test_sliding_truth_equals_python_sets_per_window():
+    """The all-windows exact truth (each pair's occurrences cover a range of window ends)
+    equals Def. 1-2 evaluated window by window with python sets, for every window end and
+    several window lengths, on a stream with repeated pairs, gaps and a host below theta."""
+    from synth import Stream, StreamRecipe
+    rng = np.random.default_rng(9)
+    n_sl, per = 9, 700
+    pk = rng.integers(0, 40, size=(n_sl * per, 2)).astype(np.uint32)
+    pk[:, 1] %= 6  # six hosts, many repeated pairs
+    pk[pk[:, 1] == 5, 0] %= 3  # host 5 has three peers only: dropped at theta_min 4
+    off = np.arange(0, n_sl * per + 1, per)
+    st = Stream(StreamRecipe("t", 0, n_sl * per, n_sl, 3, 1, 1.0, []), pk, off,
+                np.zeros(0, np.uint32), np.zeros(0, np.int64))
+    card = truth.sliding_cardinalities(st, [1, 2, 4, 12], 4)
+    assert 5 not in card[1][0].tolist()
+    for k in (1, 2, 4, 12):
+        hosts, counts = card[k]
+        for cur in range(1, n_sl + 1):
+            want = {}
+            for src, dst in pk[off[max(1, cur - k + 1) - 1]:off[cur]].tolist():
+                want.setdefault(dst, set()).add(src)
+            got = dict(zip(hosts.tolist(), counts[:, cur - 1].tolist()))
+            assert got == {h: len(v) for h, v in want.items() if h != 5}, (k, cur)
+            th, tc = truth.sliding_super_points(card, k, cur, 30)
+            assert th.tolist() == sorted(h for h, v in want.items() if len(v) >= 30)
+
+
 def test_c1_scan_reports_planted(c1_oracle, c1_stream):
     """Every planted host is reported; unsaturated estimates are near the truth."""
     res, cands = c1_oracle.scan(5, 1024.0)
