@@ -140,24 +140,47 @@ int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, con
                        uint32_t m, uint32_t slice, void* stream);
 
 /* Launch shape of the ingest kernels: blocks per compute unit for sps_ingest and
- * sps_ingest_batched, and the tile (pairs per work item) of sps_ingest_batched.  Chosen by
- * sps_autotune_ingest or set directly (0 keeps the current value). */
+ * sps_ingest_batched, the tile (pairs per work item) of sps_ingest_batched, and the number
+ * of host classes the pairs are partitioned into (1, 2, 4 or 8): every block reads all pairs
+ * and writes those of its class, and blocks of one class run on 8 / host_classes of the 8
+ * XCDs, so the recorders of one host are written through as few L2 caches as that allows.
+ * Chosen by sps_autotune_ingest or set directly (0 keeps the current value).  Defaults:
+ * 16 blocks per CU, tiles of 4096 pairs, 8 host classes. */
 typedef struct sps_tuning {
   uint32_t blocks_per_cu;
   uint32_t batch_tile;
+  uint32_t host_classes;
 } sps_tuning;
 int sps_get_tuning(const sps_sketch* s, sps_tuning* out);
 int sps_set_tuning(sps_sketch* s, const sps_tuning* t);
 
 /* Autotuner: ingests the given batch (exactly like sps_ingest_batched; for m == 1 like
  * sps_ingest) once per candidate launch shape, timing each with HIP events, and keeps the
- * fastest shape in every sketch of h_s.  Re-ingesting the same pairs at the same slice is
+ * fastest shape in every sketch of h_s.  Candidates: blocks per CU in {2, 4, 8, 16, 32, 64}
+ * x host classes in {1, 8}, and for m > 1 also tiles in {512, 2048, 8192, 32768}, in that
+ * nesting order (blocks outermost).  Re-ingesting the same pairs at the same slice is
  * idempotent, so the resulting state equals a single ingest.  Synchronous.  *best (may be
  * NULL) receives the chosen shape; h_ms (may be NULL, h_ms_cap entries) the time of each
- * candidate in the order tried. */
+ * candidate in the order tried.  The choice is also recorded in the process's tuning cache
+ * under (device architecture, sketch shape, m > 1). */
 int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, const size_t* h_n,
                         uint32_t m, uint32_t slice, void* stream, sps_tuning* best,
                         float* h_ms, uint32_t h_ms_cap);
+
+/* Tuning cache: launch shapes chosen by sps_autotune_ingest, keyed by the device
+ * architecture name (e.g. "gfx950"), the sketch shape (q, r, delta, eta, q', r', eta',
+ * delta', mode) and whether the batched ingest (m > 1) was tuned.  sps_tuning_lookup sets
+ * *found to 1 and *out to the entry for `arch` (NULL: the current device's architecture),
+ * p and batched, else *found = 0.  sps_tuning_cache_save writes every entry to a JSON file
+ * ({"sps_tuning_cache": 1, "entries": [...]}, one entry object per line);
+ * sps_tuning_cache_load adds the entries of such a file (replacing equal keys) and returns
+ * SPS_EINVAL for a file it cannot read or parse (nothing added); sps_tuning_cache_clear
+ * empties the cache.  Thread-safe; host only. */
+int sps_tuning_lookup(const char* arch, const sps_params* p, uint32_t batched, sps_tuning* out,
+                      int* found);
+int sps_tuning_cache_save(const char* path);
+int sps_tuning_cache_load(const char* path);
+int sps_tuning_cache_clear(void);
 
 /* ---- stream capture ------------------------------------------------------------------------
  * Every library call that only launches kernels (ingest, batched ingest, reset, merge,
@@ -169,6 +192,12 @@ int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
 typedef struct sps_graph sps_graph;
 int sps_graph_begin(void* stream);
 int sps_graph_end(void* stream, sps_graph** out);
+/* End capturing `stream` and make g run the newly captured work: when the new capture has
+ * the same topology as g's graph (same kernels in the same order; only arguments differ),
+ * g's executable graph is updated in place (hipGraphExecUpdate, no instantiation) and
+ * *updated (may be NULL) is set to 1; otherwise g is re-instantiated from the new capture
+ * and *updated is 0.  g must not be executing (wait for its last launch first). */
+int sps_graph_end_update(void* stream, sps_graph* g, int* updated);
 int sps_graph_launch(sps_graph* g, void* stream);
 int sps_graph_destroy(sps_graph* g);
 
@@ -339,9 +368,29 @@ int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);
  *   store per lane -- the access pattern of the ingest with no hashing of packets.
  * sps_probe_stream: reads `bytes` (multiple of 16) of device memory with 16-byte lane loads
  *   and writes one u32 checksum to d_sum -- the access pattern of the scan's first stage. */
+/* Replay probe of the ingest (measurement only).  sps_probe_replay_record writes to d_cells
+ * (device, cap u32 entries) every state cell that sps_ingest(s, d_pkts, n) would write, as an
+ * index in u16 units into the SRE array followed by the SLE array (the SLE array starts at
+ * its offset in the sketch's block), grouped into 8 regions by the ingest's host class;
+ * h_class_off (host, 9 entries) receives the region offsets and, in h_class_off[8], the
+ * total.  Returns SPS_ECAPACITY (offsets filled, nothing recorded) when the total exceeds
+ * cap.  Synchronous; allocates 64 bytes of device memory for its counters.  sps_probe_replay
+ * stores `value` into every recorded cell of s's state, region c from the blocks the ingest
+ * gives host class c (the same XCD), with the ingest's launch shape: the ingest's stores
+ * without reading or hashing pairs.  Sliding mode only. */
+int sps_probe_replay_record(const sps_sketch* s, const sps_pkt* d_pkts, size_t n,
+                            uint32_t* d_cells, size_t cap, uint64_t* h_class_off, void* stream);
+int sps_probe_replay(sps_sketch* s, const uint32_t* d_cells, const uint64_t* h_class_off,
+                     uint16_t value, void* stream);
 int sps_probe_scatter(uint16_t* d_cells, uint64_t cells, uint64_t n_stores, uint32_t seed,
                       uint16_t value, void* stream);
 int sps_probe_stream(const void* d_buf, uint64_t bytes, uint32_t* d_sum, void* stream);
+
+/* Completion time of stream work: when `stream` reaches this point (everything queued
+ * before it has finished), the host's CLOCK_MONOTONIC time in seconds is stored to *h_time
+ * (host memory that must stay valid until then).  A host function on the stream; the stream
+ * waits for it.  Not for use under stream capture. */
+int sps_stream_host_time(double* h_time, void* stream);
 
 /* Wait for all work the library queued on `stream`; reports asynchronous HIP errors. */
 int sps_sync(void* stream);

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <stddef.h>
 #include <string.h>
+#include <time.h>
 
 #include <atomic>
 #include <mutex>
@@ -186,6 +187,65 @@ int device_cu_count() {
   return n;
 }
 
+// ---- tuning cache ----------------------------------------------------------------------
+// Key: architecture name and (q, r, delta, eta, q', r', eta', delta', mode, batched).
+struct TuneEntry {
+  char arch[64];
+  uint32_t k[10];
+  sps_tuning t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+constexpr const char* kTuneLineFmt =
+    "{\"arch\": \"%s\", \"q\": %u, \"r\": %u, \"delta\": %u, \"eta\": %u, \"qp\": %u, "
+    "\"rp\": %u, \"etap\": %u, \"deltap\": %u, \"mode\": %u, \"batched\": %u, "
+    "\"blocks_per_cu\": %u, \"batch_tile\": %u, \"host_classes\": %u}";
+constexpr const char* kTuneLineScan =
+    "{\"arch\": \"%63[^\"]\", \"q\": %u, \"r\": %u, \"delta\": %u, \"eta\": %u, "
+    "\"qp\": %u, \"rp\": %u, \"etap\": %u, \"deltap\": %u, \"mode\": %u, \"batched\": %u, "
+    "\"blocks_per_cu\": %u, \"batch_tile\": %u, \"host_classes\": %u}%n";
+
+void tune_key(const sps_params& p, bool batched, uint32_t* k) {
+  const uint32_t v[10] = {p.q, p.r, p.delta, p.eta, p.qp, p.rp, p.etap, p.deltap, p.mode,
+                          batched ? 1u : 0u};
+  memcpy(k, v, sizeof(v));
+}
+
+bool tune_key_equal(const TuneEntry& e, const char* arch, const sps_params& p, bool batched) {
+  uint32_t k[10];
+  tune_key(p, batched, k);
+  return strcmp(e.arch, arch) == 0 && memcmp(e.k, k, sizeof(k)) == 0;
+}
+
+void tune_cache_put(const char* arch, const sps_params& p, bool batched, const sps_tuning& t) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (TuneEntry& e : g_tune) {
+    if (tune_key_equal(e, arch, p, batched)) {
+      e.t = t;
+      return;
+    }
+  }
+  TuneEntry e{};
+  snprintf(e.arch, sizeof(e.arch), "%s", arch);
+  tune_key(p, batched, e.k);
+  e.t = t;
+  g_tune.push_back(e);
+}
+
+// Architecture name of a device without feature suffixes ("gfx950").
+int device_arch(int dev, char* out) {
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  size_t n = 0;
+  while (n < 63 && prop.gcnArchName[n] && prop.gcnArchName[n] != ':') {
+    out[n] = prop.gcnArchName[n];
+    ++n;
+  }
+  out[n] = 0;
+  return SPS_OK;
+}
+
 }  // namespace
 
 namespace sps {
@@ -250,6 +310,59 @@ int sps_probe_scatter(uint16_t* d_cells, uint64_t cells, uint64_t n_stores, uint
 int sps_probe_stream(const void* d_buf, uint64_t bytes, uint32_t* d_sum, void* stream) {
   if (!d_buf || !d_sum || (bytes & 15u)) return SPS_EINVAL;
   SPS_HIP(sps::launch_probe_stream(d_buf, bytes, d_sum, device_cu_count(), (hipStream_t)stream));
+  return SPS_OK;
+}
+
+int sps_probe_replay_record(const sps_sketch* s, const sps_pkt* d_pkts, size_t n,
+                            uint32_t* d_cells, size_t cap, uint64_t* h_class_off, void* stream) {
+  if (!s || !h_class_off || (n && !d_pkts) || (cap && !d_cells)) return SPS_EINVAL;
+  if (s->p.mode != SPS_MODE_SLIDING) return SPS_EINVAL;
+  const uint64_t sle_off = (uint64_t)(s->dev.slea - s->dev.sre);
+  if (sle_off + (uint64_t)s->dev.rp * s->dev.row_stride > 0xFFFFFFFFull) return SPS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* d_pos = nullptr;
+  SPS_HIP(hipMalloc((void**)&d_pos, 8 * sizeof(unsigned long long)));
+  unsigned long long pos[8] = {};
+  int rc = SPS_OK;
+  hipError_t e = hipMemcpyAsync(d_pos, pos, sizeof(pos), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = sps::launch_probe_record(s->dev, d_pkts, n, (uint32_t)sle_off, nullptr, d_pos, false, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(pos, d_pos, sizeof(pos), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    uint64_t acc = 0;
+    for (int c = 0; c < 8; ++c) {
+      h_class_off[c] = acc;
+      acc += pos[c];
+      pos[c] = h_class_off[c];
+    }
+    h_class_off[8] = acc;
+    if (acc > cap) {
+      rc = SPS_ECAPACITY;
+    } else {
+      e = hipMemcpyAsync(d_pos, pos, sizeof(pos), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = sps::launch_probe_record(s->dev, d_pkts, n, (uint32_t)sle_off, d_cells, d_pos, true,
+                                     st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+  }
+  if (e != hipSuccess) rc = hip_fail(e, "sps_probe_replay_record");
+  (void)hipFree(d_pos);
+  return rc;
+}
+
+int sps_probe_replay(sps_sketch* s, const uint32_t* d_cells, const uint64_t* h_class_off,
+                     uint16_t value, void* stream) {
+  if (!s || !h_class_off || s->p.mode != SPS_MODE_SLIDING) return SPS_EINVAL;
+  sps::ClassOffsets co{};
+  for (int c = 0; c < 9; ++c) {
+    co.off[c] = h_class_off[c];
+    if (c && co.off[c] < co.off[c - 1]) return SPS_EINVAL;
+  }
+  if (co.off[8] && !d_cells) return SPS_EINVAL;
+  SPS_HIP(sps::launch_probe_replay(s->state, d_cells, co, value,
+                                   s->n_cu * (int)s->tune.blocks_per_cu, (hipStream_t)stream));
   return SPS_OK;
 }
 
@@ -352,6 +465,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   s->mlp.w = nullptr;
   s->tune.blocks_per_cu = 16;
   s->tune.batch_tile = 4096;
+  s->tune.host_classes = 8;
   // zero state and workspace once, synchronously
   SPS_HIP(hipMemset(s->base, 0, L.total));
   SPS_HIP(hipDeviceSynchronize());
@@ -382,7 +496,8 @@ int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, v
   int rc = check_slice(s, slice);
   if (rc) return rc;
   SPS_HIP(sps::launch_ingest(s->dev, d_pkts, n, (uint16_t)slice,
-                             s->n_cu * (int)s->tune.blocks_per_cu, 256, (hipStream_t)stream));
+                             s->n_cu * (int)s->tune.blocks_per_cu, 256, s->tune.host_classes,
+                             (hipStream_t)stream));
   s->cur = slice;
   return SPS_OK;
 }
@@ -406,7 +521,8 @@ int ingest_batched_with(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
     }
     tb.tile_start[k] = acc;
     SPS_HIP(sps::launch_ingest_batched(h_s[0]->dev, tb, k, tile, (uint16_t)slice,
-                                       h_s[0]->n_cu * (int)t.blocks_per_cu, 256, st));
+                                       h_s[0]->n_cu * (int)t.blocks_per_cu, 256, t.host_classes,
+                                       st));
   }
   return SPS_OK;
 }
@@ -444,8 +560,10 @@ int sps_set_tuning(sps_sketch* s, const sps_tuning* t) {
   if (!s || !t) return SPS_EINVAL;
   if (t->blocks_per_cu > 256 || (t->batch_tile && (t->batch_tile < 64 || t->batch_tile > (1u << 24))))
     return SPS_EINVAL;
+  if (t->host_classes > 8 || (t->host_classes & (t->host_classes - 1u))) return SPS_EINVAL;
   if (t->blocks_per_cu) s->tune.blocks_per_cu = t->blocks_per_cu;
   if (t->batch_tile) s->tune.batch_tile = t->batch_tile;
+  if (t->host_classes) s->tune.host_classes = t->host_classes;
   return SPS_OK;
 }
 
@@ -457,12 +575,15 @@ int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
   hipStream_t st = (hipStream_t)stream;
   static const uint32_t kBlocks[] = {2, 4, 8, 16, 32, 64};
   static const uint32_t kTiles[] = {512, 2048, 8192, 32768};
+  static const uint32_t kClasses[] = {1, 8};
   std::vector<sps_tuning> cands;
   for (uint32_t b : kBlocks) {
-    if (m == 1) {
-      cands.push_back({b, h_s[0]->tune.batch_tile});
-    } else {
-      for (uint32_t t : kTiles) cands.push_back({b, t});
+    for (uint32_t c : kClasses) {
+      if (m == 1) {
+        cands.push_back({b, h_s[0]->tune.batch_tile, c});
+      } else {
+        for (uint32_t t : kTiles) cands.push_back({b, t, c});
+      }
     }
   }
   hipEvent_t e0, e1;
@@ -476,7 +597,8 @@ int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
       SPS_HIP(hipEventRecord(e0, st));
       if (m == 1) {
         SPS_HIP(sps::launch_ingest(h_s[0]->dev, h_pkts[0], h_n[0], (uint16_t)slice,
-                                   h_s[0]->n_cu * (int)c.blocks_per_cu, 256, st));
+                                   h_s[0]->n_cu * (int)c.blocks_per_cu, 256, c.host_classes,
+                                   st));
       } else {
         rc = ingest_batched_with(h_s, h_pkts, h_n, m, slice, st, c);
         if (rc) return rc;
@@ -502,6 +624,98 @@ int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
     h_s[j]->cur = slice;
   }
   if (best) *best = pick;
+  char arch[64];
+  if (device_arch(h_s[0]->device, arch) == SPS_OK) tune_cache_put(arch, h_s[0]->p, m > 1, pick);
+  return SPS_OK;
+}
+
+int sps_tuning_lookup(const char* arch, const sps_params* p, uint32_t batched, sps_tuning* out,
+                      int* found) {
+  if (!p || !out || !found) return SPS_EINVAL;
+  *found = 0;
+  char cur[64];
+  if (!arch) {
+    int dev = 0;
+    SPS_HIP(hipGetDevice(&dev));
+    int rc = device_arch(dev, cur);
+    if (rc) return rc;
+    arch = cur;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const TuneEntry& e : g_tune) {
+    if (tune_key_equal(e, arch, *p, batched != 0)) {
+      *out = e.t;
+      *found = 1;
+      break;
+    }
+  }
+  return SPS_OK;
+}
+
+int sps_tuning_cache_save(const char* path) {
+  if (!path) return SPS_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return SPS_EINVAL;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  fprintf(f, "{\"sps_tuning_cache\": 1, \"entries\": [\n");
+  for (size_t i = 0; i < g_tune.size(); ++i) {
+    const TuneEntry& e = g_tune[i];
+    fprintf(f, kTuneLineFmt, e.arch, e.k[0], e.k[1], e.k[2], e.k[3], e.k[4], e.k[5], e.k[6],
+            e.k[7], e.k[8], e.k[9], e.t.blocks_per_cu, e.t.batch_tile, e.t.host_classes);
+    fprintf(f, "%s\n", i + 1 < g_tune.size() ? "," : "");
+  }
+  fprintf(f, "]}\n");
+  const bool ok = fclose(f) == 0;
+  return ok ? SPS_OK : SPS_EINVAL;
+}
+
+int sps_tuning_cache_load(const char* path) {
+  if (!path) return SPS_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return SPS_EINVAL;
+  std::vector<TuneEntry> got;
+  char line[512];
+  bool header = false, bad = false;
+  while (fgets(line, sizeof(line), f)) {
+    if (strstr(line, "\"sps_tuning_cache\": 1")) {
+      header = true;
+      continue;
+    }
+    const char* p = line;
+    while (*p == ' ' || *p == '\t') ++p;
+    if (*p != '{') continue;  // closing bracket and blank lines
+    TuneEntry e{};
+    int used = 0;
+    const int n = sscanf(p, kTuneLineScan, e.arch, &e.k[0], &e.k[1], &e.k[2], &e.k[3], &e.k[4],
+                         &e.k[5], &e.k[6], &e.k[7], &e.k[8], &e.k[9], &e.t.blocks_per_cu,
+                         &e.t.batch_tile, &e.t.host_classes, &used);
+    if (n != 14 || used == 0 || e.t.blocks_per_cu == 0 || e.t.blocks_per_cu > 256 ||
+        e.t.batch_tile < 64 || e.t.host_classes == 0 || e.t.host_classes > 8 ||
+        (e.t.host_classes & (e.t.host_classes - 1u)) || e.k[9] > 1) {
+      bad = true;
+      break;
+    }
+    got.push_back(e);
+  }
+  fclose(f);
+  if (!header || bad) return SPS_EINVAL;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const TuneEntry& e : got) {
+    bool replaced = false;
+    for (TuneEntry& x : g_tune) {
+      if (strcmp(x.arch, e.arch) == 0 && memcmp(x.k, e.k, sizeof(e.k)) == 0) {
+        x.t = e.t;
+        replaced = true;
+      }
+    }
+    if (!replaced) g_tune.push_back(e);
+  }
+  return SPS_OK;
+}
+
+int sps_tuning_cache_clear(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
   return SPS_OK;
 }
 
@@ -533,6 +747,49 @@ int sps_graph_end(void* stream, sps_graph** out) {
     return SPS_ENOMEM;
   }
   *out = r;
+  return SPS_OK;
+}
+
+int sps_graph_end_update(void* stream, sps_graph* g, int* updated) {
+  if (!g) return SPS_EINVAL;
+  if (updated) *updated = 0;
+  hipGraph_t ng = nullptr;
+  SPS_HIP(hipStreamEndCapture((hipStream_t)stream, &ng));
+  hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+  hipGraphNode_t bad = nullptr;
+  hipError_t err = hipGraphExecUpdate(g->exec, ng, &bad, &res);
+  if (err == hipSuccess && res == hipGraphExecUpdateSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    g->graph = ng;
+    if (updated) *updated = 1;
+    return SPS_OK;
+  }
+  (void)hipGetLastError();  // a refused update leaves an error behind; the graph is rebuilt
+  hipGraphExec_t e = nullptr;
+  err = hipGraphInstantiate(&e, ng, nullptr, nullptr, 0);
+  if (err != hipSuccess) {
+    (void)hipGraphDestroy(ng);
+    return hip_fail(err, "hipGraphInstantiate");
+  }
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  g->graph = ng;
+  g->exec = e;
+  return SPS_OK;
+}
+
+namespace {
+// Host function run by the stream: stores the host's CLOCK_MONOTONIC time in seconds.
+void store_host_time(void* p) {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  *static_cast<volatile double*>(p) = (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+}  // namespace
+
+int sps_stream_host_time(double* h_time, void* stream) {
+  if (!h_time) return SPS_EINVAL;
+  SPS_HIP(hipLaunchHostFunc((hipStream_t)stream, store_host_time, h_time));
   return SPS_OK;
 }
 

@@ -99,7 +99,7 @@ class ProfScope {
 
 // Launchers (sps_kernels.hip).
 hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
-                         int blocks, int threads, hipStream_t st);
+                         int blocks, int threads, uint32_t host_classes, hipStream_t st);
 
 struct BatchItem {
   uint16_t* sre;
@@ -113,7 +113,7 @@ struct BatchTable {
 };
 hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t m,
                                  uint32_t tile, uint16_t stamp, int blocks, int threads,
-                                 hipStream_t st);
+                                 uint32_t host_classes, hipStream_t st);
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st);
 hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream_t st);
@@ -123,6 +123,15 @@ hipError_t prepare_join();  // allows the join its LDS (call before the first sc
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
                        int n_cu, hipStream_t st);
+// Region offsets of the replay probe's cell list, one region per host class (XCD).
+struct ClassOffsets {
+  uint64_t off[9];
+};
+hipError_t launch_probe_record(const Dev& d, const sps_pkt* pkts, uint64_t n, uint32_t sle_off,
+                               uint32_t* cells, unsigned long long* pos, bool fill,
+                               hipStream_t st);
+hipError_t launch_probe_replay(uint16_t* state, const uint32_t* cells, const ClassOffsets& co,
+                               uint16_t value, int blocks, hipStream_t st);
 hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_stores,
                                 uint32_t seed, uint16_t value, int n_cu, hipStream_t st);
 hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, int n_cu,

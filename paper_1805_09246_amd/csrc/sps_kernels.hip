@@ -43,25 +43,20 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // cell and RHFG[i](aip) the SRE of row i (Alg. 3, Eq. 6 with shift (i-1)*delta).  Every
 // store writes the same stamp, so plain u16 stores are race-free maxima.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__ sre,
-                                            uint16_t* __restrict__ slea, uint32_t src,
-                                            uint32_t dst, uint16_t stamp) {
+// Cells a pair writes: emit(cell, false) for its SLE cell in each of the r' rows (index into
+// the SLE array), then, when it is sampled, emit(cell, true) for its SRE cell in each of the
+// r rows (index into the SRE array).
+template <class Emit>
+__device__ __forceinline__ void pair_cells(const Dev& d, uint32_t src, uint32_t dst, Emit&& emit) {
   const uint32_t aip = d.anet_side ? src : dst;
   const uint32_t bip = d.anet_side ? dst : src;
   const uint32_t z = fmix32(bip ^ d.seed_h3) & (d.etap - 1u);
   const uint32_t qpmask = (1u << d.qp) - 1u;
-  const bool bits = d.mode == SPS_MODE_DISCRETE;  // uniform
-  uint32_t* const slea_w = reinterpret_cast<uint32_t*>(slea);
-  uint32_t* const sre_w = reinterpret_cast<uint32_t*>(sre);
 #pragma unroll
   for (int i = 0; i < kMaxRP; ++i) {
     if (i < (int)d.rp) {
       const uint32_t j = fmix32(aip ^ d.seed_lh[i]) & qpmask;
-      const uint64_t cell = (uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z;
-      if (bits)
-        atomicOr(&slea_w[cell >> 5], 1u << (cell & 31u));
-      else
-        slea[cell] = stamp;
+      emit((uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z, false);
     }
   }
   const uint32_t h1 = fmix32(bip ^ d.seed_h1);
@@ -71,13 +66,22 @@ __device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__
     const uint32_t c0 = fmix32(aip ^ d.seed_rhfg0) & qmask;
     for (uint32_t i = 0; i < d.r; ++i) {
       const uint32_t col = i == 0 ? c0 : ((aip >> ((i - 1u) * d.delta)) ^ c0) & qmask;
-      const uint64_t cell = ((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e;
-      if (bits)
-        atomicOr(&sre_w[cell >> 5], 1u << (cell & 31u));
-      else
-        sre[cell] = stamp;
+      emit(((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e, true);
     }
   }
+}
+
+__device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__ sre,
+                                            uint16_t* __restrict__ slea, uint32_t src,
+                                            uint32_t dst, uint16_t stamp) {
+  const bool bits = d.mode == SPS_MODE_DISCRETE;  // uniform
+  pair_cells(d, src, dst, [&](uint64_t cell, bool in_sre) {
+    uint16_t* const a = in_sre ? sre : slea;
+    if (bits)
+      atomicOr(&reinterpret_cast<uint32_t*>(a)[cell >> 5], 1u << (cell & 31u));
+    else
+      a[cell] = stamp;
+  });
 }
 
 // XCD-aware ingest.  A host's recorders are written from one XCD only, so the repeated
@@ -87,6 +91,7 @@ __device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__
 // packets and keeps those whose host class (top bits of a multiplicative hash of aip) is its
 // position in the group.  The stores are the same plain stamp stores in any order.
 constexpr uint32_t kXcds = 8;
+static_assert(sizeof(ClassOffsets) == (kXcds + 1) * 8, "one region per host class");
 
 __device__ __forceinline__ uint32_t host_class(uint32_t aip) { return (aip * 0x9E3779B1u) >> 29; }
 
@@ -102,11 +107,19 @@ __global__ void __launch_bounds__(256) k_ingest(Dev d, const u32x2* __restrict__
   }
 }
 
+// Host classes: 1, 2, 4 or 8 (blocks b and b + n_cls share a class; with 8 a class is one
+// XCD, with fewer a class spans 8 / n_cls XCDs), fewer when the grid is smaller than that.
+uint32_t ingest_classes(int blocks, uint32_t host_classes) {
+  uint32_t c = host_classes >= 1u && host_classes <= kXcds ? host_classes : kXcds;
+  while (c > 1u && blocks < (int)c) c >>= 1;
+  return c;
+}
+
 hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
-                         int blocks, int threads, hipStream_t st) {
+                         int blocks, int threads, uint32_t host_classes, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint64_t need = (n + threads - 1) / threads;
-  uint32_t n_cls = blocks >= (int)kXcds ? kXcds : 1u;
+  const uint32_t n_cls = ingest_classes(blocks, host_classes);
   uint64_t b = (uint64_t)blocks / n_cls * n_cls;
   if (b > need * n_cls) b = need * n_cls;
   if (b < n_cls) b = n_cls;
@@ -147,10 +160,10 @@ __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uin
 
 hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t m,
                                  uint32_t tile, uint16_t stamp, int blocks, int threads,
-                                 hipStream_t st) {
+                                 uint32_t host_classes, hipStream_t st) {
   const uint64_t total = t.tile_start[m];
   if (total == 0) return hipSuccess;
-  const uint32_t n_cls = blocks >= (int)kXcds ? kXcds : 1u;
+  const uint32_t n_cls = ingest_classes(blocks, host_classes);
   uint64_t b = (uint64_t)blocks / n_cls * n_cls;
   if (b > total * n_cls) b = total * n_cls;
   if (b < n_cls) b = n_cls;
@@ -1555,6 +1568,74 @@ __global__ void __launch_bounds__(256) k_probe_stream(const u32x4* __restrict__ 
   }
   acc = wave_sum(acc);
   if (lane_id() == 0) atomicAdd(sum, acc);
+}
+
+// Replay probe: exactly the stores of an ingest -- the same cells and stamp, issued from the
+// XCD the ingest's host-class partition sends them to -- taken from a recorded list of cell
+// indices instead of hashed pairs.  k_probe_record (one pair per lane) counts the cells of
+// each host class (fill = 0; pos[c] accumulates) or, with pos[c] preset to the classes'
+// region offsets, writes each pair's cells as u32 indices into the SRE-then-SLE state
+// (u16 units) into its class's region (fill = 1).
+__global__ void __launch_bounds__(256) k_probe_record(Dev d, const u32x2* __restrict__ pkts,
+                                                      uint64_t n, uint32_t sle_off,
+                                                      uint32_t* __restrict__ cells,
+                                                      unsigned long long* __restrict__ pos,
+                                                      uint32_t fill) {
+  __shared__ uint32_t cnt[kXcds];
+  __shared__ unsigned long long base[kXcds];
+  if (threadIdx.x < kXcds) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t cls = 0, mine = 0;
+  u32x2 pk = {0u, 0u};
+  if (i < n) {
+    pk = pkts[i];
+    cls = host_class(d.anet_side ? pk.x : pk.y) & (kXcds - 1u);
+    uint32_t m = 0;
+    pair_cells(d, pk.x, pk.y, [&](uint64_t, bool) { ++m; });
+    mine = atomicAdd(&cnt[cls], m);
+  }
+  __syncthreads();
+  if (threadIdx.x < kXcds)
+    base[threadIdx.x] = atomicAdd(&pos[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+  __syncthreads();
+  if (fill && i < n) {
+    uint64_t o = base[cls] + mine;
+    pair_cells(d, pk.x, pk.y, [&](uint64_t cell, bool in_sre) {
+      cells[o++] = (uint32_t)(in_sre ? cell : sle_off + cell);
+    });
+  }
+}
+
+__global__ void __launch_bounds__(256) k_probe_replay(uint16_t* __restrict__ state,
+                                                      const uint32_t* __restrict__ cells,
+                                                      ClassOffsets co, uint16_t v) {
+  const uint32_t cls = blockIdx.x % kXcds;
+  const uint64_t stride = (uint64_t)(gridDim.x / kXcds) * blockDim.x;
+  const uint64_t end = co.off[cls + 1];
+  for (uint64_t i = co.off[cls] + (uint64_t)(blockIdx.x / kXcds) * blockDim.x + threadIdx.x;
+       i < end; i += stride)
+    state[cells[i]] = v;
+}
+
+hipError_t launch_probe_record(const Dev& d, const sps_pkt* pkts, uint64_t n, uint32_t sle_off,
+                               uint32_t* cells, unsigned long long* pos, bool fill,
+                               hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  ProfScope ps(SPS_STAGE_PROBE, st);
+  hipLaunchKernelGGL(k_probe_record, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, d,
+                     reinterpret_cast<const u32x2*>(pkts), n, sle_off, cells, pos,
+                     fill ? 1u : 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_replay(uint16_t* state, const uint32_t* cells, const ClassOffsets& co,
+                               uint16_t value, int blocks, hipStream_t st) {
+  uint32_t b = (uint32_t)blocks / kXcds * kXcds;
+  if (b < kXcds) b = kXcds;
+  ProfScope ps(SPS_STAGE_PROBE, st);
+  hipLaunchKernelGGL(k_probe_replay, dim3(b), dim3(256), 0, st, state, cells, co, value);
+  return hipGetLastError();
 }
 
 hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_stores,

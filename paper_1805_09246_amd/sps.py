@@ -35,7 +35,9 @@ EXPORTS = [
     "sps_estimate_hosts", "sps_mlp_work_bytes", "sps_mlp_grad", "sps_mlp_adam",
     "sps_mlp_forward", "sps_get_tuning", "sps_set_tuning", "sps_autotune_ingest",
     "sps_graph_begin", "sps_graph_end", "sps_graph_launch", "sps_graph_destroy", "sps_rebase",
-    "sps_mlp_grad_noalloc",
+    "sps_mlp_grad_noalloc", "sps_probe_replay_record", "sps_probe_replay",
+    "sps_graph_end_update", "sps_tuning_lookup", "sps_tuning_cache_save",
+    "sps_tuning_cache_load", "sps_tuning_cache_clear", "sps_stream_host_time",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
           "estimate", "sort", "features", "probe", "mlp", "scan", "rebase"]
@@ -43,7 +45,8 @@ SLICE_MAX = 65534
 
 
 class sps_tuning(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_uint32), ("batch_tile", C.c_uint32)]
+    _fields_ = [("blocks_per_cu", C.c_uint32), ("batch_tile", C.c_uint32),
+                ("host_classes", C.c_uint32)]
 
 
 class SpsError(RuntimeError):
@@ -98,9 +101,15 @@ def lib():
             "sps_get_tuning": [vp, P(sps_tuning)],
             "sps_set_tuning": [vp, P(sps_tuning)],
             "sps_autotune_ingest": [P(vp), P(vp), P(sz), u32, u32, vp, P(sps_tuning), vp, u32],
+            "sps_tuning_lookup": [C.c_char_p, P(sps_params), u32, P(sps_tuning), P(i32)],
+            "sps_tuning_cache_save": [C.c_char_p],
+            "sps_tuning_cache_load": [C.c_char_p],
+            "sps_tuning_cache_clear": [],
+            "sps_stream_host_time": [vp, vp],
             "sps_graph_begin": [vp],
             "sps_graph_end": [vp, P(vp)],
             "sps_graph_launch": [vp, vp],
+            "sps_graph_end_update": [vp, vp, P(i32)],
             "sps_graph_destroy": [vp],
             "sps_state_bytes": [vp, P(sz)],
             "sps_export": [vp, vp, sz, vp],
@@ -113,6 +122,8 @@ def lib():
             "sps_profile_read": [vp, vp, i32],
             "sps_probe_scatter": [vp, u64, u64, u32, C.c_uint16, vp],
             "sps_probe_stream": [vp, u64, vp, vp],
+            "sps_probe_replay_record": [vp, vp, sz, vp, sz, P(u64), vp],
+            "sps_probe_replay": [vp, vp, P(u64), C.c_uint16, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -394,21 +405,49 @@ def sps_probe_scatter(d_cells: torch.Tensor, n_stores: int, seed: int, value: in
                                    _stream(stream)), "sps_probe_scatter")
 
 
+def sps_probe_replay_record(h, pkts: torch.Tensor, stream=None):
+    """(cells, class offsets): the cells sps_ingest(h, pkts) writes, grouped by host class."""
+    n = _check_pairs(pkts, "sps_probe_replay_record")
+    off = (C.c_uint64 * 9)()
+    rc = lib().sps_probe_replay_record(h, _dptr(pkts) if n else None, n, None, 0, off,
+                                       _stream(stream))
+    if rc not in (SPS_OK, SPS_ECAPACITY):
+        _check(rc, "sps_probe_replay_record")
+    cells = torch.empty(max(1, off[8]), dtype=torch.int32, device=pkts.device)
+    _check(lib().sps_probe_replay_record(h, _dptr(pkts) if n else None, n, _dptr(cells),
+                                         cells.numel(), off, _stream(stream)),
+           "sps_probe_replay_record")
+    return cells, (C.c_uint64 * 9)(*off)
+
+
+def sps_probe_replay(h, cells: torch.Tensor, class_off, value: int, stream=None):
+    _check(lib().sps_probe_replay(h, _dptr(cells), class_off, value, _stream(stream)),
+           "sps_probe_replay")
+
+
 def sps_probe_stream(d_buf: torch.Tensor, d_sum: torch.Tensor, stream=None):
     nbytes = d_buf.numel() * d_buf.element_size()
     _check(lib().sps_probe_stream(_dptr(d_buf), nbytes, _dptr(d_sum), _stream(stream)),
            "sps_probe_stream")
 
 
+def _tuning_dict(t) -> dict:
+    return {"blocks_per_cu": t.blocks_per_cu, "batch_tile": t.batch_tile,
+            "host_classes": t.host_classes}
+
+
 def sps_get_tuning(h) -> dict:
     t = sps_tuning()
     _check(lib().sps_get_tuning(h, C.byref(t)), "sps_get_tuning")
-    return {"blocks_per_cu": t.blocks_per_cu, "batch_tile": t.batch_tile}
+    return _tuning_dict(t)
 
 
-def sps_set_tuning(h, blocks_per_cu: int = 0, batch_tile: int = 0):
-    t = sps_tuning(blocks_per_cu, batch_tile)
+def sps_set_tuning(h, blocks_per_cu: int = 0, batch_tile: int = 0, host_classes: int = 0):
+    t = sps_tuning(blocks_per_cu, batch_tile, host_classes)
     _check(lib().sps_set_tuning(h, C.byref(t)), "sps_set_tuning")
+
+
+AUTOTUNE_CANDIDATES_SINGLE, AUTOTUNE_CANDIDATES_BATCHED = 12, 48
 
 
 def sps_autotune_ingest(hs, pkts_list, slice_: int, stream=None):
@@ -418,8 +457,31 @@ def sps_autotune_ingest(hs, pkts_list, slice_: int, stream=None):
     ms = np.zeros(64, dtype=np.float32)
     _check(lib().sps_autotune_ingest(harr, parr, narr, m, slice_, _stream(stream), C.byref(best),
                                      ms.ctypes.data_as(C.c_void_p), 64), "sps_autotune_ingest")
-    n = 6 if m == 1 else 24
-    return {"blocks_per_cu": best.blocks_per_cu, "batch_tile": best.batch_tile}, ms[:n].tolist()
+    n = AUTOTUNE_CANDIDATES_SINGLE if m == 1 else AUTOTUNE_CANDIDATES_BATCHED
+    return _tuning_dict(best), ms[:n].tolist()
+
+
+def sps_tuning_lookup(params: dict, batched: bool, arch: str | None = None):
+    """The cached tuning dict for (arch, sketch shape, batched), or None."""
+    p = make_params(params)
+    t = sps_tuning()
+    found = C.c_int(0)
+    _check(lib().sps_tuning_lookup(arch.encode() if arch is not None else None, C.byref(p),
+                                   1 if batched else 0, C.byref(t), C.byref(found)),
+           "sps_tuning_lookup")
+    return _tuning_dict(t) if found.value else None
+
+
+def sps_tuning_cache_save(path: str):
+    _check(lib().sps_tuning_cache_save(path.encode()), "sps_tuning_cache_save")
+
+
+def sps_tuning_cache_load(path: str):
+    _check(lib().sps_tuning_cache_load(path.encode()), "sps_tuning_cache_load")
+
+
+def sps_tuning_cache_clear():
+    _check(lib().sps_tuning_cache_clear(), "sps_tuning_cache_clear")
 
 
 def sps_graph_begin(stream=None):
@@ -430,6 +492,21 @@ def sps_graph_end(stream=None):
     g = C.c_void_p(0)
     _check(lib().sps_graph_end(_stream(stream), C.byref(g)), "sps_graph_end")
     return g
+
+
+def sps_graph_end_update(g, stream=None) -> bool:
+    """End the capture and update g with it; True when updated in place."""
+    u = C.c_int(0)
+    _check(lib().sps_graph_end_update(_stream(stream), g, C.byref(u)), "sps_graph_end_update")
+    return bool(u.value)
+
+
+def sps_stream_host_time(h_time: np.ndarray, stream=None):
+    """h_time: float64 numpy array; element 0 receives the host CLOCK_MONOTONIC seconds when
+    the stream reaches this point.  The caller keeps the array alive until then."""
+    assert h_time.dtype == np.float64 and h_time.flags.c_contiguous and h_time.size >= 1
+    _check(lib().sps_stream_host_time(h_time.ctypes.data_as(C.c_void_p), _stream(stream)),
+           "sps_stream_host_time")
 
 
 def sps_graph_launch(g, stream=None):

@@ -1,5 +1,6 @@
 """The C-ABI library loads and exports every symbol include/sps.h declares; host-only entry
 points (parameter validation, sizes, error strings) work without a GPU."""
+import json
 import os
 import re
 
@@ -109,3 +110,45 @@ def test_packet_batches_rejected_before_launch():
             sps.sps_autotune_ingest([h], [bad], 1)
     with pytest.raises(ValueError):
         sps.sps_ingest_batched([h], [host, host], 1)  # one sketch, two batches
+
+
+def test_tuning_cache_file_round_trip(tmp_path):
+    """The tuning cache reads back what it writes, keys entries by architecture, shape and
+    batched flag, replaces equal keys on load, and refuses malformed files whole."""
+    from paper_1805_09246_amd import sps
+    shape = dict(q=14, r=11, delta=2, eta=8, qp=16, rp=5, etap=1024, deltap=1024, theta=1024,
+                 anet_side=0, seed=1)
+    sps.sps_tuning_cache_clear()
+    assert sps.sps_tuning_lookup(shape, False, arch="gfx950") is None
+    f = tmp_path / "tune.json"
+    f.write_text(
+        '{"sps_tuning_cache": 1, "entries": [\n'
+        '{"arch": "gfx950", "q": 14, "r": 11, "delta": 2, "eta": 8, "qp": 16, "rp": 5, '
+        '"etap": 1024, "deltap": 1024, "mode": 0, "batched": 0, "blocks_per_cu": 32, '
+        '"batch_tile": 4096, "host_classes": 8},\n'
+        '{"arch": "gfx950", "q": 14, "r": 11, "delta": 2, "eta": 8, "qp": 16, "rp": 5, '
+        '"etap": 1024, "deltap": 1024, "mode": 0, "batched": 1, "blocks_per_cu": 8, '
+        '"batch_tile": 2048, "host_classes": 1}\n]}\n')
+    sps.sps_tuning_cache_load(str(f))
+    one = sps.sps_tuning_lookup(shape, False, arch="gfx950")
+    assert one == {"blocks_per_cu": 32, "batch_tile": 4096, "host_classes": 8}
+    assert sps.sps_tuning_lookup(shape, True, arch="gfx950") == \
+        {"blocks_per_cu": 8, "batch_tile": 2048, "host_classes": 1}
+    assert sps.sps_tuning_lookup(shape, False, arch="gfx942") is None
+    assert sps.sps_tuning_lookup(dict(shape, qp=15), False, arch="gfx950") is None
+    out = tmp_path / "out.json"
+    sps.sps_tuning_cache_save(str(out))
+    json.loads(out.read_text())  # valid JSON
+    sps.sps_tuning_cache_clear()
+    sps.sps_tuning_cache_load(str(out))
+    assert sps.sps_tuning_lookup(shape, False, arch="gfx950") == one
+    # a file with a bad entry adds nothing
+    bad = tmp_path / "bad.json"
+    bad.write_text(f.read_text().replace('"host_classes": 1', '"host_classes": 3'))
+    sps.sps_tuning_cache_clear()
+    with pytest.raises(sps.SpsError):
+        sps.sps_tuning_cache_load(str(bad))
+    assert sps.sps_tuning_lookup(shape, False, arch="gfx950") is None
+    with pytest.raises(sps.SpsError):
+        sps.sps_tuning_cache_load(str(tmp_path / "missing.json"))
+    sps.sps_tuning_cache_clear()

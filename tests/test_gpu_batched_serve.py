@@ -47,6 +47,25 @@ def test_graph_capture_replays_match_eager():
     assert np.array_equal(eager.export(), graphed.export())
 
 
+@pytest.mark.parametrize("classes", [1, 2, 4, 8])
+def test_ingest_host_classes_keep_state_exact(classes):
+    """Every host-class partition of the ingest (and of the batched ingest) writes the same
+    recorders: the state equals the oracle's."""
+    rng = np.random.default_rng(20 + classes)
+    a, b, c = sps.Sketch(SMALL), sps.Sketch(SMALL), sps.Sketch(SMALL)
+    oa, ob, oc = (oracle.OracleSketch(SMALL) for _ in range(3))
+    for g in (a, b, c):
+        sps.sps_set_tuning(g.h, host_classes=classes)
+    for s in (1, 2):
+        pa, pb, pc = (_rand_pkts(rng, n) for n in (70000, 5000, 33000))
+        a.ingest(dev_pkts(pa), s)
+        sps.sps_ingest_batched([b.h, c.h], [dev_pkts(pb), dev_pkts(pc)], s)
+        for o, p in ((oa, pa), (ob, pb), (oc, pc)):
+            o.ingest(p, s)
+    for g, o in ((a, oa), (b, ob), (c, oc)):
+        assert_state_equal(g, o)
+
+
 def test_autotune_keeps_state_exact():
     rng = np.random.default_rng(2)
     sizes = [100000, 3000, 0, 250000]
@@ -56,8 +75,12 @@ def test_autotune_keeps_state_exact():
         ps = [_rand_pkts(rng, n) for n in sizes]
         if s == 1:
             best, ms = sps.sps_autotune_ingest([g.h for g in gs], [dev_pkts(p) for p in ps], s)
-            assert best["blocks_per_cu"] > 0 and len(ms) == 24 and min(ms) > 0
+            assert best["blocks_per_cu"] > 0 and min(ms) > 0
+            assert len(ms) == sps.AUTOTUNE_CANDIDATES_BATCHED
+            assert best["host_classes"] in (1, 8)
             assert sps.sps_get_tuning(gs[0].h) == best
+            # the choice is in the tuning cache under this device's architecture
+            assert sps.sps_tuning_lookup(SMALL, True) == best
         else:
             sps.sps_ingest_batched([g.h for g in gs], [dev_pkts(p) for p in ps], s)
         for o, p in zip(os_, ps):
@@ -67,7 +90,8 @@ def test_autotune_keeps_state_exact():
     one = sps.Sketch(SMALL)
     p = _rand_pkts(rng, 50000)
     best, ms = sps.sps_autotune_ingest([one.h], [dev_pkts(p)], 3)
-    assert len(ms) == 6
+    assert len(ms) == sps.AUTOTUNE_CANDIDATES_SINGLE
+    assert sps.sps_tuning_lookup(SMALL, False) == best
     o = oracle.OracleSketch(SMALL)
     o.ingest(p, 3)
     assert_state_equal(one, o)
@@ -108,6 +132,23 @@ def _serve(routers, schedule, n_slices, budget_sketches=8, use_graph=True):
         srv.collect()
     srv.collect(block=True)
     return srv
+
+
+def test_stream_host_time_marks_completion():
+    """The stream's host notification fires after the work queued before it and stores a
+    CLOCK_MONOTONIC time between the launch and the host's wait."""
+    import time
+    g = sps.Sketch(SMALL)
+    rng = np.random.default_rng(9)
+    st = torch.cuda.Stream()
+    t = np.zeros(1, dtype=np.float64)
+    t0 = time.clock_gettime(time.CLOCK_MONOTONIC)
+    with torch.cuda.stream(st):
+        g.ingest(dev_pkts(_rand_pkts(rng, 300000)), 1, st)
+        sps.sps_stream_host_time(t, st)
+    st.synchronize()
+    t1 = time.clock_gettime(time.CLOCK_MONOTONIC)
+    assert t0 <= t[0] <= t1
 
 
 def test_serving_result_same_alone_and_in_mix():
