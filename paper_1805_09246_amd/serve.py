@@ -5,8 +5,17 @@ takes everything that has arrived so far -- whatever arrived while the previous 
 on the GPU joins this one -- and launches one captured graph: a single batched ingest of all
 those batches into their routers' sketches (sps_ingest_batched), then a scan of every
 resident router (sps_scan_async).  The graph of slice s runs while batches for slice s+1
-accumulate; results are collected when its completion event fires.  Latency of a batch is
-the time from its arrival to the report of the slice that ingested it.
+accumulate.  Behind each slice's graph the stream runs a host notification
+(sps_stream_host_time) that stores the host clock when the slice's GPU work has finished;
+results are copied back and filed as reports by `collect`, which the loop calls between
+launches.  Latency of a batch is the time from its arrival to the completion of the slice
+that ingested it (`latencies`, independent of when the loop gets round to collecting);
+`report_latencies` run to the filing of the report.  Times are CLOCK_MONOTONIC seconds.
+
+Each of the `depth` result buffers has its own executable graph.  A new slice's capture is
+applied to the buffer's graph in place when only kernel arguments changed (the usual case:
+the same number of batched-ingest launches and resident routers); otherwise that graph is
+instantiated again.  Host time of capture, update and instantiation is recorded per slice.
 
 Routers are admitted while their sketch fits the device-memory budget; a router that cannot
 be admitted waits (its batches are held) until a resident router leaves and frees a slot.
@@ -29,6 +38,12 @@ import torch
 from . import sps
 
 
+def now() -> float:
+    """Host clock of arrivals and completions: CLOCK_MONOTONIC seconds (the clock the
+    library's stream notification reads)."""
+    return time.clock_gettime(time.CLOCK_MONOTONIC)
+
+
 @dataclasses.dataclass
 class Report:
     router: int
@@ -36,10 +51,12 @@ class Report:
     results: np.ndarray        # sps_result records, ascending by host
     batches: int
     packets: int
-    latencies: list            # seconds, one per batch ingested in this slice
+    latencies: list            # seconds, one per batch ingested in this slice: arrival to the
+                               # completion of the slice's work on the GPU
     info_flags: int = 0        # scan info flags: bit 0 candidate list overflowed its capacity,
                                # bit 1 more hosts kept than the result buffer holds
     kept: int = 0              # hosts the scan kept (results holds min(kept, result_cap))
+    report_latencies: list = dataclasses.field(default_factory=list)  # arrival to report
 
     @property
     def complete(self) -> bool:
@@ -84,10 +101,12 @@ class Server:
         self.slice_no = start_slice   # internal slice number (the sketches' time base)
         self.slice_base = 0            # slices shifted out by rebases
         self.rebases = 0
-        self.inflight = collections.deque()
         self.reports: list[Report] = []
         self.refused = 0
         self.incomplete = 0        # reports whose scan overflowed a buffer
+        self.graphs = [None] * depth          # one executable graph per result buffer
+        self.host_ms = {"capture": [], "update": [], "instantiate": []}
+        self.inflight = collections.deque()
 
     # ---------------------------------------------------------------- admission
     def used_bytes(self) -> int:
@@ -143,7 +162,7 @@ class Server:
     # ---------------------------------------------------------------- arrivals
     def submit(self, router: int, pkts: torch.Tensor, arrival: float | None = None):
         """Queue a device-resident batch (n x 2 int32) for the next slice launch."""
-        t = time.perf_counter() if arrival is None else arrival
+        t = now() if arrival is None else arrival
         with self.lock:
             slot = self.by_router.get(router)
             if slot is None:
@@ -171,7 +190,7 @@ class Server:
             for s, _ in active:
                 if s.sketch.cur < s_no:
                     s.sketch.advance(s_no)
-            graph = None
+            t0 = now()
             if self.use_graph:
                 sps.sps_graph_begin(st)
             try:
@@ -184,15 +203,26 @@ class Server:
                                        st)
             finally:
                 if self.use_graph:
-                    graph = sps.sps_graph_end(st)
-            if graph is not None:
-                sps.sps_graph_launch(graph, st)
+                    t1 = now()
+                    # the buffer's previous slice has been collected, so its graph is idle
+                    if self.graphs[par] is None:
+                        self.graphs[par] = sps.sps_graph_end(st)
+                        kind = "instantiate"
+                    else:
+                        kind = "update" if sps.sps_graph_end_update(self.graphs[par], st) \
+                            else "instantiate"
+                    self.host_ms["capture"].append(1e3 * (t1 - t0))
+                    self.host_ms[kind].append(1e3 * (now() - t1))
+            if self.use_graph:
+                sps.sps_graph_launch(self.graphs[par], st)
+            t_gpu = np.zeros(1, dtype=np.float64)  # written by the host notification
+            sps.sps_stream_host_time(t_gpu, st)
             done = torch.cuda.Event()
             done.record(st)
         per_router = collections.defaultdict(list)
         for slot, p, t in batch:
             per_router[slot.router].append((p.shape[0], t))
-        self.inflight.append((abs_no, done, graph, active, per_router))
+        self.inflight.append((abs_no, done, t_gpu, active, per_router))
 
     def _rebase(self, offset: int):
         """Shift the time base of every sketch that holds stamps by `offset` (stream-ordered
@@ -206,20 +236,18 @@ class Server:
         self.rebases += 1
 
     def collect(self, block: bool = False, limit: int = 1 << 30):
-        """Turn finished slices into reports (in slice order)."""
+        """Turn finished slices into reports, in slice order (block: wait for them)."""
         while self.inflight and limit > 0:
-            s_no, done, graph, active, per_router = self.inflight[0]
+            s_no, done, t_gpu, active, per_router = self.inflight[0]
             if not block and not done.query():
                 return
             done.synchronize()
-            t_done = time.perf_counter()
             self.inflight.popleft()
             limit -= 1
-            if graph is not None:
-                sps.sps_graph_destroy(graph)
             par = s_no % self.depth
             info = self.info[par].cpu().numpy()
             res = self.res[par].cpu().numpy()
+            t_done, t_rep = float(t_gpu[0]), now()
             for slot, router in active:
                 kept = int(info[slot.index, sps.INFO_KEPT])
                 flags = int(info[slot.index, sps.INFO_FLAGS])
@@ -227,9 +255,38 @@ class Server:
                 r = res[slot.index].view(sps.RESULT_DTYPE)[:n].copy()
                 b = per_router.get(router, [])
                 self.reports.append(Report(router, s_no, r, len(b), sum(x[0] for x in b),
-                                           [t_done - t for _, t in b], flags, kept))
+                                           [t_done - t for _, t in b], flags, kept,
+                                           [t_rep - t for _, t in b]))
                 if flags:
                     self.incomplete += 1
+
+    def close(self):
+        """Collect launched slices and free the graphs and sketches."""
+        try:
+            self.collect(block=True)
+        finally:
+            for g in self.graphs:
+                if g is not None:
+                    sps.sps_graph_destroy(g)
+            self.graphs = [None] * self.depth
+            for s in self.slots:
+                s.sketch.close()
+
+    def autotune(self, batches, slice_: int = 1):
+        """Pick the batched-ingest launch shape on a representative set of batches
+        [(router, pkts)] of resident routers (sps_autotune_ingest), then reset those routers'
+        sketches, so serving starts from empty sketches with the tuned shape."""
+        with self.lock:
+            slots = [self.by_router[r] for r, _ in batches]
+        best, ms = sps.sps_autotune_ingest([s.sketch.h for s in slots], [p for _, p in batches],
+                                           slice_, self.stream)
+        for s in self.slots:
+            sps.sps_set_tuning(s.sketch.h, **best)
+        with torch.cuda.stream(self.stream):
+            for s in {id(x): x for x in slots}.values():
+                s.sketch.reset()
+        self.stream.synchronize()
+        return best, ms
 
 
 def poisson_schedule(seed: int, rate_pkts: float, duration_s: float, n_routers: int,
@@ -256,14 +313,14 @@ def run_simulation(server: Server, pool: torch.Tensor, schedule, slice_s: float,
     t_arr, routers, sizes = schedule
     g = np.random.Generator(np.random.Philox(seed))
     offs = g.integers(0, pool.shape[0] - sizes.max(), len(sizes))
-    t0 = time.perf_counter()
+    t0 = now()
     stop = threading.Event()
 
     def arrivals():
         for i in range(len(t_arr)):
             if stop.is_set():
                 return
-            dt = t0 + t_arr[i] - time.perf_counter()
+            dt = t0 + t_arr[i] - now()
             if dt > 0:
                 time.sleep(dt)
             o = int(offs[i])
@@ -273,16 +330,16 @@ def run_simulation(server: Server, pool: torch.Tensor, schedule, slice_s: float,
     th.start()
     for k in range(n_slices):
         target = t0 + (k + 1) * slice_s
-        dt = target - time.perf_counter()
+        dt = target - now()
         if dt > 0:
             time.sleep(dt)
         server.run_slice()
-        server.collect(block=False)
+        server.collect()
         if departures and (k + 1) in departures:
             for r in departures[k + 1]:
                 server.release(r)
     stop.set()
     th.join()
     server.collect(block=True)
-    wall = time.perf_counter() - t0
+    wall = now() - t0
     return wall, int(sizes[t_arr < n_slices * slice_s].sum())
