@@ -78,6 +78,7 @@ def lib():
         L.or_splitmix64_export.argtypes = [C.c_uint64]
         L.or_set_slice.argtypes = [vp, C.c_uint32]
         L.or_ingest.argtypes = [vp, vp, C.c_uint64, C.c_uint32]
+        L.or_ingest_threads.argtypes = [vp, vp, C.c_uint64, C.c_uint32, C.c_uint32]
         L.or_merge.argtypes = [vp, P(vp), C.c_uint32]
         L.or_rebase.argtypes = [vp, C.c_uint32]
         L.or_row_live.argtypes = [vp, C.c_uint32, vp]
@@ -184,6 +185,12 @@ class OracleSketch:
     def ingest(self, pkts: np.ndarray, slice_: int) -> int:
         pkts = np.ascontiguousarray(pkts, dtype=np.uint32)
         return int(lib().or_ingest(self._h, _ptr(pkts), pkts.shape[0], slice_))
+
+    def ingest_threads(self, pkts: np.ndarray, slice_: int, threads: int | None = None) -> int:
+        """The same update with the rows split over threads (state identical to ingest)."""
+        pkts = np.ascontiguousarray(pkts, dtype=np.uint32)
+        return int(lib().or_ingest_threads(self._h, _ptr(pkts), pkts.shape[0], slice_,
+                                           threads or default_threads()))
 
     def set_slice(self, slice_: int) -> int:
         return int(lib().or_set_slice(self._h, slice_))

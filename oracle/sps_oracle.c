@@ -277,6 +277,63 @@ int or_ingest(or_sketch *s, const uint32_t *pkts, uint64_t n, uint32_t slice) {
   return OR_OK;
 }
 
+/* The same update on several threads: the work is cut by row -- the r SRE rows (Alg. 3)
+ * and the r' SLE rows (Alg. 6) are separate tasks, handed to the threads round robin --
+ * and every thread walks all packets writing only its rows' cells.  No cell belongs to two
+ * tasks, so the state equals or_ingest's for any thread count. */
+typedef struct {
+  or_sketch *s;
+  const uint32_t *pkts;
+  uint64_t n;
+  uint32_t slice, first, step;
+} or_ingest_job;
+
+static void *or_ingest_worker(void *arg) {
+  or_ingest_job *j = (or_ingest_job *)arg;
+  or_sketch *s = j->s;
+  uint32_t task;
+  for (task = j->first; task < s->p.r + s->p.rp; task += j->step) {
+    uint64_t k;
+    for (k = 0; k < j->n; k++) {
+      uint32_t src = j->pkts[2 * k], dst = j->pkts[2 * k + 1];
+      uint32_t aip = s->p.anet_side == 0 ? dst : src;
+      uint32_t bip = s->p.anet_side == 0 ? src : dst;
+      if (task < s->p.r) {
+        if (or_lsb(or_H1(s, bip)) >= s->tau)
+          *or_sre_cell(s, task, or_RHFG(s, task, aip), or_H2(s, bip)) = (uint16_t)j->slice;
+      } else {
+        uint32_t i = task - s->p.r;
+        *or_slea_cell(s, i, (uint64_t)or_LH(s, i, aip) * s->p.deltap + or_H3(s, bip)) =
+            (uint16_t)j->slice;
+      }
+    }
+  }
+  return NULL;
+}
+
+int or_ingest_threads(or_sketch *s, const uint32_t *pkts, uint64_t n, uint32_t slice,
+                      uint32_t nthreads) {
+  pthread_t th[64];
+  or_ingest_job jobs[64];
+  uint32_t t;
+  int rc = or_set_slice(s, slice);
+  if (rc != OR_OK) return rc;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 64) nthreads = 64;
+  if (nthreads > s->p.r + s->p.rp) nthreads = s->p.r + s->p.rp;
+  for (t = 0; t < nthreads; t++) {
+    jobs[t].s = s;
+    jobs[t].pkts = pkts;
+    jobs[t].n = n;
+    jobs[t].slice = slice;
+    jobs[t].first = t;
+    jobs[t].step = nthreads;
+    pthread_create(&th[t], NULL, or_ingest_worker, &jobs[t]);
+  }
+  for (t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+  return OR_OK;
+}
+
 /* ------------------------------------------------------------------------------------- */
 /* Merge: Alg. 2 and Alg. 7, cell-wise, keeping the most recent observation (max stamp).  */
 /* dst <- max(dst, src_0, ..., src_{n-1}).                                               */

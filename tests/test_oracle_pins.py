@@ -448,6 +448,21 @@ def test_merge_union():
     assert merged.merge([oracle.OracleSketch(other)]) == -3
 
 
+def test_threaded_ingest_equals_plain_ingest(c1_stream):
+    """Splitting the ingest's rows over threads writes the same cells (any thread count)."""
+    from synth.configs import C1_PARAMS
+    a = oracle.OracleSketch(C1_PARAMS)
+    for s in (1, 2, 3):
+        a.ingest(c1_stream.slice_pkts(s), s)
+    for threads in (1, 3, 16):
+        b = oracle.OracleSketch(C1_PARAMS)
+        for s in (1, 2, 3):
+            assert b.ingest_threads(c1_stream.slice_pkts(s), s, threads) == 0
+        assert np.array_equal(a.sre(), b.sre()) and np.array_equal(a.slea(), b.slea())
+        assert b.cur == 3
+    assert oracle.OracleSketch(C1_PARAMS).ingest_threads(c1_stream.slice_pkts(1), 0) != 0
+
+
 def test_order_independence():
     sl = _small_stream(4)
     a, b = oracle.OracleSketch(SMALL), oracle.OracleSketch(SMALL)
