@@ -52,7 +52,9 @@ extern "C" {
 /* ---- scan info words (sps_scan_async's d_info, 8 x u32) ---------------------------------- */
 #define SPS_INFO_KEPT 0      /* hosts kept by the final filter */
 #define SPS_INFO_CAND 1      /* candidates recovered from the SRE array (may exceed capacity) */
-#define SPS_INFO_FLAGS 2     /* bit 0: candidate buffer overflow; bit 1: result buffer overflow */
+#define SPS_INFO_FLAGS 2     /* bit 0: candidate buffer overflow; bit 1: result buffer overflow;
+                                bit 2 (with bit 0): candidate search not run -- its expected size
+                                from the rows' hot rates passed 2^36 nodes (SRE array saturated) */
 #define SPS_INFO_HSE0 3      /* hot SREs in row 0 */
 #define SPS_INFO_HSE1 4      /* hot SREs in row 1 */
 #define SPS_INFO_NODES_LO 5  /* candidate-search nodes expanded (low 32 bits; Alg. 4-5 tuples */
@@ -81,7 +83,10 @@ typedef struct sps_pkt {
  *     recorder -- the rough estimator RE (Sec. 3.2) and linear estimator LE (Sec. 4) of a
  *     discrete time window, 16 times smaller.  A discrete sketch holds every pair since its
  *     last sps_reset; its scans take window 1 (k = 1), its merge is a bitwise or, and
- *     sps_features is not available.  Recorders are set with 32-bit atomic or. */
+ *     sps_features is not available.  Recorders are set with 32-bit atomic or.
+ *   row_counts: 1 -> the sketch keeps per-row stamp histograms (sliding mode only; see
+ *     sps_ingest): scans skip the sweep of the SLE array, ingests cost one 32-bit
+ *     compare-and-swap per SLE cell they change.  0 -> plain stores, scans sweep. */
 #define SPS_MODE_SLIDING 0u
 #define SPS_MODE_DISCRETE 1u
 typedef struct sps_params {
@@ -92,6 +97,7 @@ typedef struct sps_params {
   uint64_t seed;
   uint32_t cand_cap;
   uint32_t mode;
+  uint32_t row_counts;
 } sps_params;
 
 /* One reported host (Alg. 8 and the final filter at the end of Sec. 4). */
@@ -126,8 +132,14 @@ int sps_reset(sps_sketch* s, void* stream);
  * the n pairs d_pkts[0..n).  Every written recorder receives `slice`.  Requires
  * 1 <= slice <= 65534 and slice >= the current slice (else SPS_ESLICE, nothing written);
  * sets the current slice.  n may be 0.  Because every write carries a stamp no smaller than
- * any stored one, plain stores equal a max and the result is independent of packet order
- * (Sec. 3.3: recorders need no synchronization). */
+ * any stored one, a write equals a max and the result is independent of packet order
+ * (Sec. 3.3: recorders need no synchronization).
+ * Row counts (params.row_counts = 1): the sketch also keeps, per SLE-array row, how many
+ * cells hold each stamp value; the ingest sets SLE cells by 32-bit compare-and-swap and moves
+ * one count per cell whose stamp it changes, so scans read the row live counts of Def. 4
+ * from these histograms instead of sweeping the SLE array.  Merging other sketches into a
+ * sketch, importing a dump or replaying a probe into it stops the counting for that sketch
+ * (its scans then sweep the array; results are the same) until its next sps_reset. */
 int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, void* stream);
 
 /* The same for m sketches (routers) at once, in one launch per 64 routers: sketch h_s[j]
@@ -145,11 +157,14 @@ int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, con
  * and writes those of its class, and blocks of one class run on 8 / host_classes of the 8
  * XCDs, so the recorders of one host are written through as few L2 caches as that allows.
  * Chosen by sps_autotune_ingest or set directly (0 keeps the current value).  Defaults:
- * 16 blocks per CU, tiles of 4096 pairs, 8 host classes. */
+ * 16 blocks per CU, tiles of 4096 pairs, 8 host classes.  scan_overlap (not tuned): 1 (the
+ * default) runs a scan's sweep of the SLE array for the row live counts on the sketch's own
+ * side stream, beside the candidate search; 2 runs everything on the scan's stream. */
 typedef struct sps_tuning {
   uint32_t blocks_per_cu;
   uint32_t batch_tile;
   uint32_t host_classes;
+  uint32_t scan_overlap;
 } sps_tuning;
 int sps_get_tuning(const sps_sketch* s, sps_tuning* out);
 int sps_set_tuning(sps_sketch* s, const sps_tuning* t);
@@ -266,7 +281,8 @@ int sps_estimate_hosts(sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_
  * replaces linear counting for a host only when its window is 10 slices, |USLE|^k >=
  * min_live, every feature x_a / eta' lies in [h_feat_lo[a], h_feat_hi[a]] (host arrays of
  * 10 floats, copied), x_0 < eta' - 1 (some age is unsaturated), and the output lies in
- * [0, log(max_card)]; otherwise linear counting is kept and SPS_F_LC_FALLBACK is set.
+ * [0, log(max_card)]; otherwise linear counting is kept and SPS_F_LC_FALLBACK is set.  When
+ * linear counting is saturated (SPS_F_SATURATED) the network can only raise its estimate.
  * Inference rounds weights and activations to bfloat16 and accumulates in float32. */
 int sps_attach_mlp(sps_sketch* s, const float* d_weights, const float* h_feat_lo,
                    const float* h_feat_hi, uint32_t min_live, double max_card);
@@ -330,7 +346,9 @@ int sps_derived(const sps_sketch* s, uint32_t* tau, uint32_t* hot_cut, uint64_t*
 
 /* Internal scan buffers of the last scan, for inspection: which = 0 hot bitmap
  * (r x 2^q bits as u32 words, bit j of word w = SRE 32w + j in row-major order), 1 candidate
- * list (u32, unordered, at most cand_cap), 2 SLE row live counts (r' x u32).  Copies
+ * list (u32, unordered, at most cand_cap), 2 SLE row live counts (r' x u32), 3 the per-row
+ * stamp histograms (r' x 65536 u32: entry [i][v] = cells of SLE-array row i with stamp v,
+ * v >= 1; size 0 when the sketch does not keep them, see sps_ingest).  Copies
  * min(bytes, size) bytes to host memory h_buf (may be NULL to query); *size gets the full
  * size.  Synchronous. */
 int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, size_t* size,
@@ -358,7 +376,8 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
 #define SPS_STAGE_MLP 11
 #define SPS_STAGE_SCAN 12
 #define SPS_STAGE_REBASE 13
-#define SPS_NSTAGES 14
+#define SPS_STAGE_SCAN_ROWS 14  /* the row-count sweep of a scan, on the sketch's side stream */
+#define SPS_NSTAGES 15
 int sps_profile_enable(uint32_t stage_mask);
 int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);
 

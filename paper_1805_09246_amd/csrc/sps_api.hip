@@ -39,6 +39,8 @@ struct sps_sketch {
   int device;
   int n_cu;
   sps_tuning tune;
+  bool hist_valid;        // dev.hist matches the SLE array (sliding mode; see k_ingest)
+  sps::ScanFork fork;     // side stream and events of the scans' row-count sweep
 };
 
 namespace {
@@ -80,6 +82,7 @@ int validate(const sps_params* p) {
   if (p->theta < 1 || p->anet_side > 1) return SPS_EINVAL;
   if (effective_cand_cap(p) > (1u << 26)) return SPS_EINVAL;
   if (p->mode > SPS_MODE_DISCRETE) return SPS_EINVAL;
+  if (p->row_counts > 1 || (p->row_counts && p->mode != SPS_MODE_SLIDING)) return SPS_EINVAL;
   return SPS_OK;
 }
 
@@ -106,7 +109,7 @@ uint64_t splitmix64_next(uint64_t& st) {
 }
 
 struct Layout {
-  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, skeys, total;
+  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, skeys, part, hist, total;
   uint64_t row_len, row_stride, sre_bytes, slea_bytes;
 };
 
@@ -137,6 +140,8 @@ Layout layout_of(const sps_params* p) {
   L.kept = o;   o += round_up(cap * sizeof(sps_result), 256);
   L.sorted = o; o += round_up(cap * sizeof(sps_result), 256);
   L.skeys = o;  o += round_up(cap * 8, 256);
+  L.part = o;   o += (uint64_t)sps::kMaxRP * sps::kRowsPartWaves * 4;
+  L.hist = o;   o += p->row_counts ? (uint64_t)p->rp * sps::kHistBins * 4 : 0;
   L.total = o;
   return L;
 }
@@ -152,10 +157,13 @@ int check_slice(const sps_sketch* s, uint32_t slice) {
   return SPS_OK;
 }
 
-struct Header {  // 64-byte dump header
+// 64-byte dump header: the parameter fields up to and including `mode` (the sketch's
+// shape; row_counts is a property of the live sketch, not of its state)
+constexpr size_t kHeaderParams = offsetof(sps_params, mode) + sizeof(uint32_t);
+struct Header {
   char magic[4];
   uint32_t cur;
-  sps_params p;
+  uint8_t params[kHeaderParams];
 };
 static_assert(sizeof(Header) == 64, "dump header is 64 bytes");
 
@@ -363,6 +371,7 @@ int sps_probe_replay(sps_sketch* s, const uint32_t* d_cells, const uint64_t* h_c
   if (co.off[8] && !d_cells) return SPS_EINVAL;
   SPS_HIP(sps::launch_probe_replay(s->state, d_cells, co, value,
                                    s->n_cu * (int)s->tune.blocks_per_cu, (hipStream_t)stream));
+  s->hist_valid = false;  // plain stores: the histograms no longer follow the cells
   return SPS_OK;
 }
 
@@ -433,6 +442,8 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.cand = reinterpret_cast<uint32_t*>(b + L.cand);
   d.kept = reinterpret_cast<sps_result*>(b + L.kept);
   d.skeys = reinterpret_cast<uint64_t*>(b + L.skeys);
+  d.rows_part = reinterpret_cast<uint32_t*>(b + L.part);
+  d.hist = p->row_counts ? reinterpret_cast<uint32_t*>(b + L.hist) : nullptr;
   s->d_info = reinterpret_cast<uint32_t*>(b + L.info);
   s->d_sorted = reinterpret_cast<sps_result*>(b + L.sorted);
   d.row_len = L.row_len;
@@ -466,9 +477,20 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   s->tune.blocks_per_cu = 16;
   s->tune.batch_tile = 4096;
   s->tune.host_classes = 8;
+  s->tune.scan_overlap = 1;
+  s->hist_valid = p->row_counts != 0;  // all zero, like the state
+  s->fork = sps::ScanFork{nullptr, nullptr, nullptr};
   // zero state and workspace once, synchronously
-  SPS_HIP(hipMemset(s->base, 0, L.total));
-  SPS_HIP(hipDeviceSynchronize());
+  hipError_t e = hipMemset(s->base, 0, L.total);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  // the scans' side stream (default priority) and its fork/join events
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->fork.side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork.ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork.ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)sps_destroy(s);
+    return hip_fail(e, "sps_create");
+  }
   *out = s;
   return SPS_OK;
 }
@@ -476,6 +498,9 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
 int sps_destroy(sps_sketch* s) {
   if (!s) return SPS_EINVAL;
   (void)hipDeviceSynchronize();
+  if (s->fork.ev_join) (void)hipEventDestroy(s->fork.ev_join);
+  if (s->fork.ev_fork) (void)hipEventDestroy(s->fork.ev_fork);
+  if (s->fork.side) (void)hipStreamDestroy(s->fork.side);
   if (s->owns) (void)hipFree(s->base);
   (void)hipHostFree(s->h_info);
 
@@ -483,9 +508,17 @@ int sps_destroy(sps_sketch* s) {
   return SPS_OK;
 }
 
+namespace {
+uint64_t hist_bytes(const sps_sketch* s) { return (uint64_t)s->dev.rp * sps::kHistBins * 4; }
+}  // namespace
+
 int sps_reset(sps_sketch* s, void* stream) {
   if (!s) return SPS_EINVAL;
   SPS_HIP(sps::launch_fill_zero(s->state, s->state_bytes, (hipStream_t)stream));
+  if (s->p.row_counts) {
+    SPS_HIP(sps::launch_fill_zero(s->dev.hist, hist_bytes(s), (hipStream_t)stream));
+    s->hist_valid = true;
+  }
   SPS_HIP(sps::launch_scan_reset(s->dev, true, (hipStream_t)stream));
   s->cur = 0;
   return SPS_OK;
@@ -497,7 +530,7 @@ int sps_ingest(sps_sketch* s, const sps_pkt* d_pkts, size_t n, uint32_t slice, v
   if (rc) return rc;
   SPS_HIP(sps::launch_ingest(s->dev, d_pkts, n, (uint16_t)slice,
                              s->n_cu * (int)s->tune.blocks_per_cu, 256, s->tune.host_classes,
-                             (hipStream_t)stream));
+                             s->hist_valid, (hipStream_t)stream));
   s->cur = slice;
   return SPS_OK;
 }
@@ -514,6 +547,7 @@ int ingest_batched_with(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
     for (uint32_t j = 0; j < k; ++j) {
       tb.item[j].sre = h_s[b + j]->dev.sre;
       tb.item[j].slea = h_s[b + j]->dev.slea;
+      tb.item[j].hist = h_s[b + j]->hist_valid ? h_s[b + j]->dev.hist : nullptr;
       tb.item[j].pkts = h_pkts[b + j];
       tb.item[j].n = h_n[b + j];
       tb.tile_start[j] = acc;
@@ -561,6 +595,8 @@ int sps_set_tuning(sps_sketch* s, const sps_tuning* t) {
   if (t->blocks_per_cu > 256 || (t->batch_tile && (t->batch_tile < 64 || t->batch_tile > (1u << 24))))
     return SPS_EINVAL;
   if (t->host_classes > 8 || (t->host_classes & (t->host_classes - 1u))) return SPS_EINVAL;
+  if (t->scan_overlap > 2) return SPS_EINVAL;
+  if (t->scan_overlap) s->tune.scan_overlap = t->scan_overlap;
   if (t->blocks_per_cu) s->tune.blocks_per_cu = t->blocks_per_cu;
   if (t->batch_tile) s->tune.batch_tile = t->batch_tile;
   if (t->host_classes) s->tune.host_classes = t->host_classes;
@@ -580,9 +616,9 @@ int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
   for (uint32_t b : kBlocks) {
     for (uint32_t c : kClasses) {
       if (m == 1) {
-        cands.push_back({b, h_s[0]->tune.batch_tile, c});
+        cands.push_back({b, h_s[0]->tune.batch_tile, c, h_s[0]->tune.scan_overlap});
       } else {
-        for (uint32_t t : kTiles) cands.push_back({b, t, c});
+        for (uint32_t t : kTiles) cands.push_back({b, t, c, h_s[0]->tune.scan_overlap});
       }
     }
   }
@@ -598,7 +634,7 @@ int sps_autotune_ingest(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, co
       if (m == 1) {
         SPS_HIP(sps::launch_ingest(h_s[0]->dev, h_pkts[0], h_n[0], (uint16_t)slice,
                                    h_s[0]->n_cu * (int)c.blocks_per_cu, 256, c.host_classes,
-                                   st));
+                                   h_s[0]->hist_valid, st));
       } else {
         rc = ingest_batched_with(h_s, h_pkts, h_n, m, slice, st, c);
         if (rc) return rc;
@@ -818,8 +854,11 @@ int sps_advance(sps_sketch* s, uint32_t slice) {
 int sps_rebase(sps_sketch* s, uint32_t offset, void* stream) {
   if (!s) return SPS_EINVAL;
   if (offset > s->cur) return SPS_ESLICE;
-  if (s->p.mode == SPS_MODE_SLIDING)
+  if (s->p.mode == SPS_MODE_SLIDING) {
     SPS_HIP(sps::launch_rebase(s->state, s->state_bytes, offset, (hipStream_t)stream));
+    if (s->hist_valid)
+      SPS_HIP(sps::launch_hist_rebase(s->dev.hist, s->dev.rp, offset, (hipStream_t)stream));
+  }
   s->cur -= offset;
   return SPS_OK;
 }
@@ -835,9 +874,12 @@ int sps_merge(sps_sketch* dst, const sps_sketch* const* h_src, uint32_t nsrc, vo
     srcs[j] = h_src[j]->state;
     if (h_src[j]->cur > cur) cur = h_src[j]->cur;
   }
+  bool other = false;
+  for (uint32_t j = 0; j < nsrc; ++j) other = other || h_src[j] != dst;
   if (nsrc)
     SPS_HIP(sps::launch_merge(dst->state, srcs, nsrc, dst->state_bytes,
                               dst->p.mode == SPS_MODE_DISCRETE, (hipStream_t)stream));
+  if (other) dst->hist_valid = false;  // merged cells are not counted; scans sweep instead
   dst->cur = cur;
   return SPS_OK;
 }
@@ -848,8 +890,10 @@ int sps_scan_async(sps_sketch* s, uint32_t window, double threshold, sps_result*
   if (window < 1 || window > 65534u) return SPS_EINVAL;
   if (s->p.mode == SPS_MODE_DISCRETE && window != 1) return SPS_EINVAL;
   if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
+  const sps::ScanFork none{nullptr, nullptr, nullptr};
   SPS_HIP(sps::launch_scan(s->dev, s->cur, window, threshold, d_out, (uint32_t)cap, d_info,
-                           s->mlp, s->n_cu, (hipStream_t)stream));
+                           s->mlp, s->hist_valid, s->tune.scan_overlap == 1 ? s->fork : none, s->n_cu,
+                           (hipStream_t)stream));
   return SPS_OK;
 }
 
@@ -891,7 +935,7 @@ int sps_estimate_hosts(sps_sketch* s, const uint32_t* d_hosts, size_t n, uint32_
   if (window < 1 || window > 65534u || n > 0xFFFFFFFFull) return SPS_EINVAL;
   if (s->p.mode == SPS_MODE_DISCRETE && window != 1) return SPS_EINVAL;
   SPS_HIP(sps::launch_estimate_hosts(s->dev, s->cur, window, d_hosts, (uint32_t)n, d_out, s->mlp,
-                                     s->n_cu, (hipStream_t)stream));
+                                     s->hist_valid, s->n_cu, (hipStream_t)stream));
   return SPS_OK;
 }
 
@@ -983,7 +1027,7 @@ int sps_export(const sps_sketch* s, void* h_buf, size_t bytes, void* stream) {
   Header h{};
   memcpy(h.magic, "SPS1", 4);
   h.cur = s->cur;
-  h.p = s->p;
+  memcpy(h.params, &s->p, kHeaderParams);
   memcpy(h_buf, &h, sizeof(h));
   uint8_t* o = static_cast<uint8_t*>(h_buf) + sizeof(Header);
   const Dev& d = s->dev;
@@ -1007,8 +1051,10 @@ int sps_import(sps_sketch* s, const void* h_buf, size_t bytes, void* stream) {
   memcpy(&h, h_buf, sizeof(h));
   sps_params want = s->p;
   if (memcmp(h.magic, "SPS1", 4) != 0) return SPS_EINVAL;
-  h.p.cand_cap = want.cand_cap;
-  if (!same_shape(h.p, want) || h.cur > 65534u) return SPS_EMISMATCH;
+  sps_params hp = want;
+  memcpy(&hp, h.params, kHeaderParams);
+  hp.cand_cap = want.cand_cap;
+  if (!same_shape(hp, want) || h.cur > 65534u) return SPS_EMISMATCH;
   hipStream_t st = (hipStream_t)stream;
   const Dev& d = s->dev;
   const uint8_t* o = static_cast<const uint8_t*>(h_buf) + sizeof(Header);
@@ -1020,6 +1066,7 @@ int sps_import(sps_sketch* s, const void* h_buf, size_t bytes, void* stream) {
   SPS_HIP(hipMemcpy2D(d.slea, pitch, o, (size_t)s->row_bytes, (size_t)s->row_bytes, d.rp,
                       hipMemcpyHostToDevice));
   s->cur = h.cur;
+  s->hist_valid = false;  // imported cells are not counted; scans sweep instead
   return SPS_OK;
 }
 
@@ -1057,6 +1104,10 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
     case 2:
       src = reinterpret_cast<const uint8_t*>(d.ctrl) + offsetof(Ctrl, last_row_live);
       full = (size_t)d.rp * 4;
+      break;
+    case 3:  // stamp histograms, only while the ingest keeps them
+      src = d.hist;
+      full = s->hist_valid ? (size_t)hist_bytes(s) : 0;
       break;
     default: return SPS_EINVAL;
   }

@@ -12,6 +12,8 @@ constexpr int kMaxRP = 8;      // SLE-array rows supported
 constexpr int kMaxR = 32;      // SRE-array rows supported
 constexpr int kMaxBatch = 64;  // routers per batched launch
 constexpr int kMaxMerge = 32;  // sources per merge launch (more are chained)
+constexpr uint32_t kHistBins = 65536;  // one bin per u16 stamp value
+constexpr uint32_t kRowsPartWaves = 4096;  // waves of the side-stream sweep (4 per CU) at most
 
 // Per-scan counters kept in device memory (one 256-byte block per sketch).  Every scan
 // leaves the working fields zero when it ends (its last kernel clears them), so a scan
@@ -24,13 +26,16 @@ struct Ctrl {
   unsigned long long join_nodes;  // nodes the candidate search expanded
   uint32_t sort_done;     // blocks of the ordering kernel done with their tiles
   uint32_t pad0;
+  uint32_t join_skipped;  // the candidate search was not run: its expected size was too large
+  uint32_t pad1;
+  uint32_t hot_rows[kMaxR];  // hot SREs of every row
   // copies of the last scan's counters, for inspection (not cleared)
   uint32_t last_row_live[kMaxRP];
   uint32_t last_n_cand;
   uint32_t last_hse[2];
-  uint32_t pad[64 - 2 * kMaxRP - 4 - 2 - 2 - 3];
+  uint32_t pad[64 - 2 * kMaxRP - 4 - 2 - 2 - 2 - kMaxR - 3];
 };
-constexpr uint32_t kCtrlWorkingWords = kMaxRP + 4 + 2 + 2;  // fields cleared after a scan
+constexpr uint32_t kCtrlWorkingWords = kMaxRP + 4 + 2 + 2 + 2 + kMaxR;  // cleared after a scan
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte block");
 
 // Learned-estimator attachment (weights in device memory, bounds by value).
@@ -54,6 +59,10 @@ struct Dev {
   sps_result* kept;       // [cand_cap] kept hosts, unordered
   uint64_t* skeys;        // [cand_cap] (host << 32 | index into kept), sorted per 4096-tile
   Ctrl* ctrl;
+  uint32_t* rows_part;    // [kMaxRP][kRowsPartWaves] per-wave row live counts of the sweep
+                          // that runs on a scan's side stream (summed by the estimate)
+  uint32_t* hist;         // [r'][kHistBins] per-row stamp histograms: hist[i][v] = cells of
+                          // SLE-array row i whose stamp is v (v >= 1; bin 0 unused)
   uint64_t row_len;       // L' = 2^q' delta' + eta' - delta'
   uint64_t row_stride;    // cells between SLE-array rows (row_len rounded up to 64)
   uint32_t q, r, delta, eta;
@@ -98,12 +107,15 @@ class ProfScope {
 };
 
 // Launchers (sps_kernels.hip).
+// track: keep d.hist exact (SLE cells set by compare-and-swap, each stamp change counted)
 hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
-                         int blocks, int threads, uint32_t host_classes, hipStream_t st);
+                         int blocks, int threads, uint32_t host_classes, bool track,
+                         hipStream_t st);
 
 struct BatchItem {
   uint16_t* sre;
   uint16_t* slea;
+  uint32_t* hist;  // the sketch's stamp histograms, or null when they are not kept
   const sps_pkt* pkts;
   uint64_t n;
 };
@@ -117,12 +129,20 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
 hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st);
 hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream_t st);
+hipError_t launch_hist_rebase(uint32_t* hist, uint32_t rows, uint32_t offset, hipStream_t st);
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
                         uint64_t bytes, bool bits, hipStream_t st);
 hipError_t prepare_join();  // allows the join its LDS (call before the first scan)
+// Side stream of a scan: the row-count sweep runs there beside the candidate search (side
+// null: everything on the scan's stream).  The two events are the fork and the join.
+struct ScanFork {
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
+};
+// use_hist: row live counts from d.hist instead of a sweep of the SLE array
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       int n_cu, hipStream_t st);
+                       bool use_hist, const ScanFork& fork, int n_cu, hipStream_t st);
 // Region offsets of the replay probe's cell list, one region per host class (XCD).
 struct ClassOffsets {
   uint64_t off[9];
@@ -140,7 +160,7 @@ hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const ui
                            uint64_t n, uint32_t* x, int n_cu, hipStream_t st);
 hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const uint32_t* hosts, uint32_t n, sps_result* out,
-                                 const MlpRef& mlp, int n_cu, hipStream_t st);
+                                 const MlpRef& mlp, bool use_hist, int n_cu, hipStream_t st);
 
 // Learned estimator (sps_mlp.hip).
 uint32_t mlp_grad_waves(uint32_t n);

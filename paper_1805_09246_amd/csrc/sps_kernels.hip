@@ -43,9 +43,9 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // cell and RHFG[i](aip) the SRE of row i (Alg. 3, Eq. 6 with shift (i-1)*delta).  Every
 // store writes the same stamp, so plain u16 stores are race-free maxima.
 // ---------------------------------------------------------------------------------------
-// Cells a pair writes: emit(cell, false) for its SLE cell in each of the r' rows (index into
-// the SLE array), then, when it is sampled, emit(cell, true) for its SRE cell in each of the
-// r rows (index into the SRE array).
+// Cells a pair writes: emit(cell, false, i) for its SLE cell in each row i < r' (index into
+// the SLE array), then, when it is sampled, emit(cell, true, i) for its SRE cell in each row
+// i < r (index into the SRE array).  Rows come in the same order on every lane.
 template <class Emit>
 __device__ __forceinline__ void pair_cells(const Dev& d, uint32_t src, uint32_t dst, Emit&& emit) {
   const uint32_t aip = d.anet_side ? src : dst;
@@ -56,7 +56,7 @@ __device__ __forceinline__ void pair_cells(const Dev& d, uint32_t src, uint32_t 
   for (int i = 0; i < kMaxRP; ++i) {
     if (i < (int)d.rp) {
       const uint32_t j = fmix32(aip ^ d.seed_lh[i]) & qpmask;
-      emit((uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z, false);
+      emit((uint64_t)i * d.row_stride + (uint64_t)j * d.deltap + z, false, (uint32_t)i);
     }
   }
   const uint32_t h1 = fmix32(bip ^ d.seed_h1);
@@ -66,19 +66,98 @@ __device__ __forceinline__ void pair_cells(const Dev& d, uint32_t src, uint32_t 
     const uint32_t c0 = fmix32(aip ^ d.seed_rhfg0) & qmask;
     for (uint32_t i = 0; i < d.r; ++i) {
       const uint32_t col = i == 0 ? c0 : ((aip >> ((i - 1u) * d.delta)) ^ c0) & qmask;
-      emit(((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e, true);
+      emit(((((uint64_t)i << d.q) + col) << __builtin_ctz(d.eta)) + e, true, i);
     }
   }
 }
 
+// Per-row stamp histograms kept by the ingest (sliding mode).  hist[i][v] counts the cells
+// of SLE-array row i whose stamp is v, so the live count of row i in a window [lo, cur]
+// (Def. 4) is the sum of bins lo..cur and a scan need not sweep the array.  An ingest at
+// stamp s changes a cell only from an older stamp `old` to s, once per cell and launch, so
+// each change moves one count from bin old to bin s.  The change is made with a 32-bit
+// compare-and-swap on the word holding the u16 cell: the lane whose swap succeeds is the one
+// that changed the cell, and every other lane sees s already (or a failed swap returns the
+// word, which changes at most twice per launch: once per cell).  Counts are gathered per
+// block in LDS -- additions to bin s per row, removals by age s - old for ages below
+// kHistNear -- and added to the histograms once per block; older removals go straight to
+// their bins.
+constexpr uint32_t kHistNear = 128;
+struct HistAgg {
+  uint32_t inc[kMaxRP];
+  uint32_t dec[kMaxRP][kHistNear];
+};
+
+__device__ __forceinline__ void hist_agg_clear(HistAgg* a) {
+  for (uint32_t j = threadIdx.x; j < (uint32_t)kMaxRP * (kHistNear + 1u); j += blockDim.x) {
+    if (j < (uint32_t)kMaxRP) a->inc[j] = 0u;
+    else a->dec[(j - kMaxRP) / kHistNear][(j - kMaxRP) % kHistNear] = 0u;
+  }
+}
+
+// The block's gathered counts into hist (called by every thread of the block, after a
+// barrier that follows the block's last change); the LDS counts are left zero.
+__device__ __forceinline__ void hist_agg_flush(HistAgg* a, uint32_t* hist, uint32_t rp,
+                                               uint32_t stamp) {
+  for (uint32_t j = threadIdx.x; j < rp * (kHistNear + 1u); j += blockDim.x) {
+    if (j < rp) {
+      const uint32_t c = a->inc[j];
+      if (c) atomicAdd(&hist[(uint64_t)j * kHistBins + stamp], c);
+      a->inc[j] = 0u;
+    } else {
+      const uint32_t row = (j - rp) / kHistNear, age = (j - rp) % kHistNear;
+      const uint32_t c = a->dec[row][age];
+      if (c) atomicSub(&hist[(uint64_t)row * kHistBins + stamp - age], c);  // age < stamp
+      a->dec[row][age] = 0u;
+    }
+  }
+}
+
+// Stamp `stamp` into SLE cell `cell` of row `row`, counting the change.
+__device__ __forceinline__ void tracked_sle_store(uint16_t* __restrict__ slea, uint32_t* hist,
+                                                  HistAgg* agg, uint64_t cell, uint32_t row,
+                                                  uint32_t stamp) {
+  uint32_t* const w = reinterpret_cast<uint32_t*>(slea) + (cell >> 1);  // rows hold even cells
+  const uint32_t sh = (uint32_t)(cell & 1u) * 16u;
+  uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t ov = 0u;
+  bool changed = false;
+  for (uint32_t tries = 0;; ++tries) {
+    ov = (old >> sh) & 0xFFFFu;
+    if (ov >= stamp) break;
+    const uint32_t nw = (old & ~(0xFFFFu << sh)) | (stamp << sh);
+    if (tries == 8u) {  // not reached: the word changes at most twice per launch
+      slea[cell] = (uint16_t)stamp;
+      break;
+    }
+    const uint32_t got = atomicCAS(w, old, nw);
+    if (got == old) {
+      changed = true;
+      break;
+    }
+    old = got;
+  }
+  const uint64_t m = __ballot(changed);
+  if (m && lane_id() == (uint32_t)__builtin_ctzll(m)) atomicAdd(&agg->inc[row], (uint32_t)__popcll(m));
+  if (changed && ov != 0u) {
+    const uint32_t age = stamp - ov;
+    if (age < kHistNear) atomicAdd(&agg->dec[row][age], 1u);
+    else atomicSub(&hist[(uint64_t)row * kHistBins + ov], 1u);
+  }
+}
+
+// kBits: the discrete variant (one bit per recorder, set by atomic or); else u16 stamps.
+template <bool kTrack, bool kBits>
 __device__ __forceinline__ void ingest_pair(const Dev& d, uint16_t* __restrict__ sre,
-                                            uint16_t* __restrict__ slea, uint32_t src,
-                                            uint32_t dst, uint16_t stamp) {
-  const bool bits = d.mode == SPS_MODE_DISCRETE;  // uniform
-  pair_cells(d, src, dst, [&](uint64_t cell, bool in_sre) {
+                                            uint16_t* __restrict__ slea, uint32_t* hist,
+                                            HistAgg* agg, uint32_t src, uint32_t dst,
+                                            uint16_t stamp) {
+  pair_cells(d, src, dst, [&](uint64_t cell, bool in_sre, uint32_t row) {
     uint16_t* const a = in_sre ? sre : slea;
-    if (bits)
+    if (kBits)
       atomicOr(&reinterpret_cast<uint32_t*>(a)[cell >> 5], 1u << (cell & 31u));
+    else if (kTrack && !in_sre)
+      tracked_sle_store(slea, hist, agg, cell, row, stamp);
     else
       a[cell] = stamp;
   });
@@ -95,15 +174,26 @@ static_assert(sizeof(ClassOffsets) == (kXcds + 1) * 8, "one region per host clas
 
 __device__ __forceinline__ uint32_t host_class(uint32_t aip) { return (aip * 0x9E3779B1u) >> 29; }
 
+template <bool kTrack, bool kBits>
 __global__ void __launch_bounds__(256) k_ingest(Dev d, const u32x2* __restrict__ pkts,
                                                 uint64_t n, uint16_t stamp, uint32_t n_cls) {
+  __shared__ HistAgg agg;
+  if (kTrack) {
+    hist_agg_clear(&agg);
+    __syncthreads();
+  }
   const uint32_t cls = blockIdx.x % n_cls, cls_mask = n_cls - 1u;
   const uint64_t stride = (uint64_t)(gridDim.x / n_cls) * blockDim.x;
   for (uint64_t i = (uint64_t)(blockIdx.x / n_cls) * blockDim.x + threadIdx.x; i < n;
        i += stride) {
     const u32x2 pk = pkts[i];
     const uint32_t aip = d.anet_side ? pk.x : pk.y;
-    if ((host_class(aip) & cls_mask) == cls) ingest_pair(d, d.sre, d.slea, pk.x, pk.y, stamp);
+    if ((host_class(aip) & cls_mask) == cls)
+      ingest_pair<kTrack, kBits>(d, d.sre, d.slea, d.hist, &agg, pk.x, pk.y, stamp);
+  }
+  if (kTrack) {
+    __syncthreads();
+    hist_agg_flush(&agg, d.hist, d.rp, stamp);
   }
 }
 
@@ -116,7 +206,8 @@ uint32_t ingest_classes(int blocks, uint32_t host_classes) {
 }
 
 hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t stamp,
-                         int blocks, int threads, uint32_t host_classes, hipStream_t st) {
+                         int blocks, int threads, uint32_t host_classes, bool track,
+                         hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint64_t need = (n + threads - 1) / threads;
   const uint32_t n_cls = ingest_classes(blocks, host_classes);
@@ -124,8 +215,16 @@ hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t
   if (b > need * n_cls) b = need * n_cls;
   if (b < n_cls) b = n_cls;
   ProfScope ps(SPS_STAGE_INGEST, st);
-  hipLaunchKernelGGL(k_ingest, dim3((uint32_t)b), dim3(threads), 0, st, d,
-                     reinterpret_cast<const u32x2*>(pkts), n, stamp, n_cls);
+  const u32x2* p2 = reinterpret_cast<const u32x2*>(pkts);
+  if (d.mode == SPS_MODE_DISCRETE)
+    hipLaunchKernelGGL((k_ingest<false, true>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
+                       n, stamp, n_cls);
+  else if (track)
+    hipLaunchKernelGGL((k_ingest<true, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
+                       n, stamp, n_cls);
+  else
+    hipLaunchKernelGGL((k_ingest<false, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
+                       n, stamp, n_cls);
   return hipGetLastError();
 }
 
@@ -133,9 +232,15 @@ hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t
 // into tiles; work items are tiles, so one launch covers uneven batches.  Block group g takes
 // tiles g, g + groups, ...; the router of a tile is found by binary search of the tile
 // prefix sums held in the kernel arguments.
+template <bool kTrack, bool kBits>
 __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uint32_t m,
                                                         uint32_t tile, uint16_t stamp,
                                                         uint32_t n_cls) {
+  __shared__ HistAgg agg;
+  if (kTrack) {
+    hist_agg_clear(&agg);
+    __syncthreads();
+  }
   // tiles go to groups of n_cls consecutive blocks, one host class per block (see k_ingest)
   const uint32_t cls = blockIdx.x % n_cls, cls_mask = n_cls - 1u;
   const uint64_t total = t.tile_start[m];
@@ -150,10 +255,21 @@ __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uin
     uint64_t last = first + tile;
     if (last > it.n) last = it.n;
     const u32x2* pk2 = reinterpret_cast<const u32x2*>(it.pkts);
+    const bool track = kTrack && it.hist != nullptr;  // uniform
     for (uint64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
       const u32x2 pk = pk2[i];
       const uint32_t aip = d.anet_side ? pk.x : pk.y;
-      if ((host_class(aip) & cls_mask) == cls) ingest_pair(d, it.sre, it.slea, pk.x, pk.y, stamp);
+      if ((host_class(aip) & cls_mask) == cls) {
+        if (track)
+          ingest_pair<kTrack, kBits>(d, it.sre, it.slea, it.hist, &agg, pk.x, pk.y, stamp);
+        else
+          ingest_pair<false, kBits>(d, it.sre, it.slea, nullptr, nullptr, pk.x, pk.y, stamp);
+      }
+    }
+    if (track) {  // this tile's counts go to its router's histograms
+      __syncthreads();
+      hist_agg_flush(&agg, it.hist, d.rp, stamp);
+      __syncthreads();
     }
   }
 }
@@ -163,13 +279,22 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
                                  uint32_t host_classes, hipStream_t st) {
   const uint64_t total = t.tile_start[m];
   if (total == 0) return hipSuccess;
+  bool track = false;
+  for (uint32_t j = 0; j < m; ++j) track = track || t.item[j].hist != nullptr;
   const uint32_t n_cls = ingest_classes(blocks, host_classes);
   uint64_t b = (uint64_t)blocks / n_cls * n_cls;
   if (b > total * n_cls) b = total * n_cls;
   if (b < n_cls) b = n_cls;
   ProfScope ps(SPS_STAGE_INGEST_BATCHED, st);
-  hipLaunchKernelGGL(k_ingest_batched, dim3((uint32_t)b), dim3(threads), 0, st, shape, t, m,
-                     tile, stamp, n_cls);
+  if (shape.mode == SPS_MODE_DISCRETE)
+    hipLaunchKernelGGL((k_ingest_batched<false, true>), dim3((uint32_t)b), dim3(threads), 0, st,
+                       shape, t, m, tile, stamp, n_cls);
+  else if (track)
+    hipLaunchKernelGGL((k_ingest_batched<true, false>), dim3((uint32_t)b), dim3(threads), 0, st,
+                       shape, t, m, tile, stamp, n_cls);
+  else
+    hipLaunchKernelGGL((k_ingest_batched<false, false>), dim3((uint32_t)b), dim3(threads), 0, st,
+                       shape, t, m, tile, stamp, n_cls);
   return hipGetLastError();
 }
 
@@ -259,6 +384,29 @@ hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream
   return hipGetLastError();
 }
 
+// Rebase of the stamp histograms: bin v takes bin v + offset (stamps at or below `offset`
+// became 0 and drop out).  One block per row; each round reads its bins before any thread
+// writes, and later rounds only read bins above every bin written so far.
+__global__ void __launch_bounds__(256) k_hist_rebase(uint32_t* __restrict__ hist,
+                                                     uint32_t offset) {
+  uint32_t* const h = hist + (uint64_t)blockIdx.x * kHistBins;
+  for (uint32_t base = 1; base < kHistBins; base += blockDim.x) {
+    const uint32_t v = base + threadIdx.x;
+    const uint32_t src = v + offset;
+    const uint32_t val = v < kHistBins && src < kHistBins ? h[src] : 0u;
+    __syncthreads();
+    if (v < kHistBins) h[v] = val;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_hist_rebase(uint32_t* hist, uint32_t rows, uint32_t offset, hipStream_t st) {
+  if (offset == 0 || rows == 0) return hipSuccess;
+  ProfScope ps(SPS_STAGE_REBASE, st);
+  hipLaunchKernelGGL(k_hist_rebase, dim3(rows), dim3(256), 0, st, hist, offset);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------
 // Scan.
 // ---------------------------------------------------------------------------------------
@@ -329,6 +477,7 @@ __device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sr
     uint32_t* hw = d.hot + (sre_idx >> 5);
     hw[0] = (uint32_t)mask;
     hw[1] = (uint32_t)(mask >> 32);
+    if (mask) atomicAdd(&d.ctrl->hot_rows[row], (uint32_t)__popcll(mask));
   }
   if (hot) {  // the join's layout: all 2^delta extensions of a node in one entry
     const uint32_t low = col & ((1u << (d.q - d.delta)) - 1u);
@@ -355,10 +504,32 @@ __device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sr
 // remaining blocks take one SRE per lane: k-weight >= hot cut marks it hot (Sec. 3.3); a
 // wave's 64 verdicts become one ballot word of the hot bitmap, and rows 0 and 1 also append
 // their hot columns to the HSE lists.
-__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t with_sre) {
+constexpr uint32_t kStatsSre = 1u;   // the SREs (hot bitmap, lists, join table, row counts)
+constexpr uint32_t kStatsHist = 2u;  // row live counts from the stamp histograms
+constexpr uint32_t kStatsRows = 4u;  // row live counts (histograms, else a sweep)
+constexpr uint32_t kStatsPartials = 8u;  // the sweep leaves per-wave counts in d.rows_part
+
+__device__ __forceinline__ void scan_stats_body(const Dev& d, uint32_t lo, uint32_t hi,
+                                                uint32_t flags) {
   __shared__ uint32_t red[kMaxRP][256 / kWave];
   const uint32_t b = blockIdx.x;
-  {
+  const bool with_sre = (flags & kStatsSre) != 0u;
+  if ((flags & kStatsRows) && (flags & kStatsHist)) {
+    // row b's live cells: the stamps lo..hi of its histogram (Def. 4 numerator)
+    if (b < d.rp) {
+      const uint32_t* h = d.hist + (uint64_t)b * kHistBins;
+      uint32_t c = 0;
+      for (uint32_t v = lo + threadIdx.x; v <= hi; v += blockDim.x) c += h[v];
+      c = wave_sum(c);
+      if (lane_id() == 0) red[0][threadIdx.x / kWave] = c;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[0][w];
+        atomicAdd(&d.ctrl->row_live[b], t);
+      }
+    }
+  } else if (flags & kStatsRows) {
     const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t first = (uint64_t)b * blockDim.x + threadIdx.x;
     uint32_t cnt[kMaxRP];
@@ -435,19 +606,34 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
       for (; v < total; v += step) account(v, live8(__builtin_nontemporal_load(&vec[v]), lo));
       add_to(row, acc);
     }
-    for (uint32_t j = 0; j < d.rp; ++j) {
-      uint32_t c = 0;
+    if (flags & kStatsPartials) {
+      // one plain store per wave and row, summed later by the estimate: no LDS (so these
+      // blocks fit on a compute unit beside the candidate search's block, which takes nearly
+      // all of it) and no same-address atomics at the end of the sweep
+      const uint32_t gw = b * (blockDim.x / kWave) + threadIdx.x / kWave;
+      for (uint32_t j = 0; j < d.rp; ++j) {
+        uint32_t c = 0;
 #pragma unroll
-      for (int jj = 0; jj < kMaxRP; ++jj)
-        if ((uint32_t)jj == j) c = cnt[jj];
-      c = wave_sum(c);
-      if (lane_id() == 0) red[j][threadIdx.x / kWave] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x < d.rp) {
-      uint32_t t = 0;
-      for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
-      atomicAdd(&d.ctrl->row_live[threadIdx.x], t);
+        for (int jj = 0; jj < kMaxRP; ++jj)
+          if ((uint32_t)jj == j) c = cnt[jj];
+        c = wave_sum(c);
+        if (lane_id() == 0) d.rows_part[(uint64_t)j * kRowsPartWaves + gw] = c;
+      }
+    } else {
+      for (uint32_t j = 0; j < d.rp; ++j) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int jj = 0; jj < kMaxRP; ++jj)
+          if ((uint32_t)jj == j) c = cnt[jj];
+        c = wave_sum(c);
+        if (lane_id() == 0) red[j][threadIdx.x / kWave] = c;
+      }
+      __syncthreads();
+      if (threadIdx.x < d.rp) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
+        atomicAdd(&d.ctrl->row_live[threadIdx.x], t);
+      }
     }
   }
   if (!with_sre) return;
@@ -457,6 +643,37 @@ __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t
   const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
   for (uint64_t g = (uint64_t)b * (blockDim.x / kWave) + wib; g < n_groups; g += n_waves)
     sre_group(d, lo, g * kWave + lane_id());
+}
+
+// The hot-SRE pass (and, with kStatsRows, the row live counts first).
+__global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t hi,
+                                                    uint32_t flags) {
+  scan_stats_body(d, lo, hi, flags);
+}
+
+// The row live counts alone, as per-wave partial counts: the sweep that runs on a scan's side
+// stream; k_rows_sum then adds up the partials.
+template <bool kBits>  // a separate symbol for the discrete variant's sweep of bits
+__global__ void __launch_bounds__(256) k_scan_rows(Dev d, uint32_t lo, uint32_t hi) {
+  scan_stats_body(d, lo, hi, kStatsRows | kStatsPartials);
+}
+
+// One block: the row live counts from the sweep's `waves` per-wave partials.
+__global__ void __launch_bounds__(256) k_rows_sum(Dev d, uint32_t waves) {
+  __shared__ uint32_t red[kMaxRP][256 / kWave];
+  for (uint32_t j = 0; j < d.rp; ++j) {
+    uint32_t c = 0;
+    for (uint32_t w = threadIdx.x; w < waves; w += blockDim.x)
+      c += d.rows_part[(uint64_t)j * kRowsPartWaves + w];
+    c = wave_sum(c);
+    if (lane_id() == 0) red[j][threadIdx.x / kWave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < d.rp) {
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
+    d.ctrl->row_live[threadIdx.x] = t;
+  }
 }
 
 // Hot extensions of a node (Alg. 4-5 check, in bulk).  Row i's SRE for the extension t is
@@ -950,6 +1167,26 @@ __device__ __forceinline__ void copy_to_lds(D* __restrict__ dst, const S* __rest
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words]
 // [count, base, next group, -, candidate buffer of kCandBuf entries].
+// Expected number of nodes of the candidate search when row i is hot at the rate
+// hot_rows[i] / 2^q independently: n0 n1 pairs, then each row multiplies by its surviving
+// extensions (2^delta values, fewer where bit 32 cuts them off) times its hot rate.
+__device__ double join_expected_nodes(const Dev& d) {
+  const Ctrl* c = d.ctrl;
+  double level = (double)c->hse_count[0] * (double)c->hse_count[1], total = level;
+  for (uint32_t i = 2; i < d.r; ++i) {
+    const uint32_t sx = (i - 2u) * d.delta + d.q;
+    const uint32_t bits = sx >= 32u ? 0u : (32u - sx < d.delta ? 32u - sx : d.delta);
+    level *= (double)(1u << bits) * ((double)c->hot_rows[i] / (double)(1u << d.q));
+    total += level;
+  }
+  return total;
+}
+
+// Above this many expected nodes (2^36, about 2000 times the search of the scale workload,
+// a few tenths of a second) the SRE array is taken as saturated for the window: the search is
+// not run and the scan reports a candidate overflow instead of running for minutes.
+constexpr double kJoinNodeBudget = 68719476736.0;
+
 template <bool kTbLds>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                                                           uint32_t list_words) {
@@ -957,6 +1194,10 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   const uint32_t q = d.q, r = d.r;
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
   if (n0 == 0u || n1 == 0u) return;
+  if (join_expected_nodes(d) > kJoinNodeBudget) {  // the same verdict in every block
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->join_skipped = 1u;
+    return;
+  }
   const uint32_t* __restrict__ tb = d.hot_t;
   uint32_t off = 0;
   if (kTbLds) {
@@ -1063,6 +1304,10 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
 // LDS holds after the hot table (when it is small) and a reserve for the hot lists; the lists
 // take whatever LDS is left.  (Two blocks of 10 waves per CU, with smaller stacks, measured
 // 7 % slower at the config-2 shape than one block of 16.)
+// LDS left free beside the join's block, so that a block of the row-count sweep (which runs
+// on a side stream during the search) fits on the same compute unit.
+constexpr uint32_t kJoinLdsSpare = 1024;
+
 struct JoinShape {
   bool tb_lds;
   uint32_t cap, waves, lds, blocks, list_words;
@@ -1079,7 +1324,7 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
   if (s.waves > kJoinWaves) s.waves = kJoinWaves;
   if (s.waves < 1u) s.waves = 1u;
-  s.lds = kLdsBytes;
+  s.lds = kLdsBytes - kJoinLdsSpare;
   s.blocks = (uint32_t)n_cu;
   s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 4u) * 4u) / 4u;
   return s;
@@ -1279,7 +1524,8 @@ __device__ void scan_finish(const Dev& d, uint32_t cap, uint32_t* __restrict__ i
     if (info) {
       info[SPS_INFO_KEPT] = c->n_kept;
       info[SPS_INFO_CAND] = c->n_cand;
-      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap ? 1u : 0u) | (c->n_kept > cap ? 2u : 0u);
+      info[SPS_INFO_FLAGS] = (c->n_cand > d.cand_cap || c->join_skipped ? 1u : 0u) |
+                             (c->n_kept > cap ? 2u : 0u) | (c->join_skipped ? 4u : 0u);
       info[SPS_INFO_HSE0] = c->hse_count[0];
       info[SPS_INFO_HSE1] = c->hse_count[1];
       info[SPS_INFO_NODES_LO] = (uint32_t)c->join_nodes;
@@ -1429,7 +1675,10 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       const bool informative = __shfl(feat, 0, kWave) < d.etap - 1u;
       const float y = mlp_forward_wave(mlp.w, lane < SPS_MLP_IN ? mlp_encode(feat, d.etap) : 0.f);
       if (U >= mlp.min_live && all_in && informative && y >= 0.f && y <= mlp.log_max) {
-        est = (double)expf(y);
+        // a saturated linear count is the largest value it can express, so the network
+        // may only raise it
+        const double e_net = (double)expf(y);
+        est = (flags & SPS_F_SATURATED) && e_net < est ? est : e_net;
         flags |= SPS_F_MLP;
       } else {
         flags |= SPS_F_LC_FALLBACK;
@@ -1455,13 +1704,25 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
 
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       int n_cu, hipStream_t st) {
+                       bool use_hist, const ScanFork& fork, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
-  // one block per CU: the SLE array streamed, then one SRE per lane for the hot SREs
+  // The row live counts are needed only by the estimate, and the sweep that makes them
+  // (HBM-bound) shares nothing with the candidate search (ALU-bound, in LDS): with a side
+  // stream the sweep is launched right after the search, beside it, and the estimate waits
+  // for both.  With histograms the counts are a few hundred bins, taken with the SRE pass.
+  const bool side = !use_hist && fork.side != nullptr && (uint32_t)n_cu * 4u <= kRowsPartWaves;
+  if (side) {  // the fork point: everything before the scan has been issued on st
+    hipError_t e = hipEventRecord(fork.ev_fork, st);
+    if (e != hipSuccess) return e;
+  }
   {
+    // one block per CU: one SRE per lane for the hot SREs (and, without a side stream, the
+    // row live counts first)
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, 1u);
+    const uint32_t rows = side ? 0u : (kStatsRows | (use_hist ? kStatsHist : 0u));
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
+                       kStatsSre | rows);
   }
   {
     ProfScope ps(SPS_STAGE_JOIN, st);
@@ -1472,6 +1733,25 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
     else
       hipLaunchKernelGGL(k_join<false>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
                          js.cap, js.list_words);
+  }
+  if (side) {
+    // the sweep, issued after the search so that the search's blocks are placed first
+    hipError_t e = hipStreamWaitEvent(fork.side, fork.ev_fork, 0);
+    if (e != hipSuccess) return e;
+    {
+      ProfScope ps(SPS_STAGE_SCAN_ROWS, fork.side);
+      if (d.mode == SPS_MODE_DISCRETE)
+        hipLaunchKernelGGL(k_scan_rows<true>, dim3((uint32_t)n_cu), dim3(256), 0, fork.side, d,
+                           lo, cur);
+      else
+        hipLaunchKernelGGL(k_scan_rows<false>, dim3((uint32_t)n_cu), dim3(256), 0, fork.side, d,
+                           lo, cur);
+      hipLaunchKernelGGL(k_rows_sum, dim3(1), dim3(256), 0, fork.side, d, (uint32_t)n_cu * 4u);
+    }
+    // the estimate needs the row live counts
+    e = hipEventRecord(fork.ev_join, fork.side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, fork.ev_join, 0);
+    if (e != hipSuccess) return e;
   }
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st);
@@ -1491,12 +1771,13 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
 // counters cleared.
 hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
                                  const uint32_t* hosts, uint32_t n, sps_result* out,
-                                 const MlpRef& mlp, int n_cu, hipStream_t st) {
+                                 const MlpRef& mlp, bool use_hist, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   {
-    // the SLE array only (with_sre = 0)
+    // row live counts only (no SREs)
     ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, 0u);
+    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
+                       kStatsRows | (use_hist ? kStatsHist : 0u));
   }
   if (n) {
     uint32_t blocks = (n + 3) / 4;
@@ -1592,7 +1873,7 @@ __global__ void __launch_bounds__(256) k_probe_record(Dev d, const u32x2* __rest
     pk = pkts[i];
     cls = host_class(d.anet_side ? pk.x : pk.y) & (kXcds - 1u);
     uint32_t m = 0;
-    pair_cells(d, pk.x, pk.y, [&](uint64_t, bool) { ++m; });
+    pair_cells(d, pk.x, pk.y, [&](uint64_t, bool, uint32_t) { ++m; });
     mine = atomicAdd(&cnt[cls], m);
   }
   __syncthreads();
@@ -1601,7 +1882,7 @@ __global__ void __launch_bounds__(256) k_probe_record(Dev d, const u32x2* __rest
   __syncthreads();
   if (fill && i < n) {
     uint64_t o = base[cls] + mine;
-    pair_cells(d, pk.x, pk.y, [&](uint64_t cell, bool in_sre) {
+    pair_cells(d, pk.x, pk.y, [&](uint64_t cell, bool in_sre, uint32_t) {
       cells[o++] = (uint32_t)(in_sre ? cell : sle_off + cell);
     });
   }

@@ -40,13 +40,13 @@ EXPORTS = [
     "sps_tuning_cache_load", "sps_tuning_cache_clear", "sps_stream_host_time",
 ]
 STAGES = ["ingest", "ingest_batched", "merge", "fill", "scan_reset", "scan_stats", "join",
-          "estimate", "sort", "features", "probe", "mlp", "scan", "rebase"]
+          "estimate", "sort", "features", "probe", "mlp", "scan", "rebase", "scan_rows"]
 SLICE_MAX = 65534
 
 
 class sps_tuning(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_uint32), ("batch_tile", C.c_uint32),
-                ("host_classes", C.c_uint32)]
+                ("host_classes", C.c_uint32), ("scan_overlap", C.c_uint32)]
 
 
 class SpsError(RuntimeError):
@@ -59,7 +59,8 @@ class sps_params(C.Structure):
     _fields_ = [("q", C.c_uint32), ("r", C.c_uint32), ("delta", C.c_uint32), ("eta", C.c_uint32),
                 ("qp", C.c_uint32), ("rp", C.c_uint32), ("etap", C.c_uint32),
                 ("deltap", C.c_uint32), ("theta", C.c_uint32), ("anet_side", C.c_uint32),
-                ("seed", C.c_uint64), ("cand_cap", C.c_uint32), ("mode", C.c_uint32)]
+                ("seed", C.c_uint64), ("cand_cap", C.c_uint32), ("mode", C.c_uint32),
+                ("row_counts", C.c_uint32)]
 
 
 RESULT_DTYPE = np.dtype([("host", "<u4"), ("live", "<u4"), ("flags", "<u4"), ("pad", "<u4"),
@@ -432,8 +433,15 @@ def sps_probe_stream(d_buf: torch.Tensor, d_sum: torch.Tensor, stream=None):
 
 
 def _tuning_dict(t) -> dict:
+    """The ingest's launch shape (what the tuner and the tuning cache hold)."""
     return {"blocks_per_cu": t.blocks_per_cu, "batch_tile": t.batch_tile,
             "host_classes": t.host_classes}
+
+
+def sps_get_scan_overlap(h) -> bool:
+    t = sps_tuning()
+    _check(lib().sps_get_tuning(h, C.byref(t)), "sps_get_tuning")
+    return t.scan_overlap == 1
 
 
 def sps_get_tuning(h) -> dict:
@@ -442,8 +450,9 @@ def sps_get_tuning(h) -> dict:
     return _tuning_dict(t)
 
 
-def sps_set_tuning(h, blocks_per_cu: int = 0, batch_tile: int = 0, host_classes: int = 0):
-    t = sps_tuning(blocks_per_cu, batch_tile, host_classes)
+def sps_set_tuning(h, blocks_per_cu: int = 0, batch_tile: int = 0, host_classes: int = 0,
+                   scan_overlap: int = 0):
+    t = sps_tuning(blocks_per_cu, batch_tile, host_classes, scan_overlap)
     _check(lib().sps_set_tuning(h, C.byref(t)), "sps_set_tuning")
 
 

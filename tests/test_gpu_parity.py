@@ -52,6 +52,27 @@ def test_c1_full_stream(c1_stream):
     g.close()
 
 
+def test_scan_with_and_without_side_stream(c1_stream):
+    """The row-count sweep on the sketch's side stream (default) and on the scan's own stream
+    give the oracle's scans; the side stream is on by default."""
+    from synth.configs import C1_PARAMS, C1_THRESHOLD, C1_WINDOW
+    g, h = sps.Sketch(C1_PARAMS), sps.Sketch(C1_PARAMS)
+    assert sps.sps_get_scan_overlap(g.h)
+    sps.sps_set_tuning(h.h, scan_overlap=2)
+    assert not sps.sps_get_scan_overlap(h.h)
+    o = oracle.OracleSketch(C1_PARAMS)
+    for s in range(1, 8):
+        p = c1_stream.slice_pkts(s)
+        g.ingest(dev_pkts(p), s)
+        h.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+        if s >= C1_WINDOW:
+            assert_scan_equal(g, o, C1_WINDOW, C1_THRESHOLD, f"side stream, slice {s}")
+            assert_scan_equal(h, o, C1_WINDOW, C1_THRESHOLD, f"one stream, slice {s}")
+    g.close()
+    h.close()
+
+
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 257, 4097, 100003])
 def test_ragged_batch_sizes(n):
     rng = np.random.default_rng(n + 1)

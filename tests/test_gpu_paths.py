@@ -183,3 +183,39 @@ def test_c3_full_size_merged_scans():
     for g in gs:
         g.close()
     merged.close()
+
+
+def test_saturated_sre_array_skips_the_search():
+    """Every SRE hot in every row (all pairs sampled, hundreds per SRE): the expected search
+    passes 2^36 nodes, so the search is not run and the scan reports a candidate overflow at
+    once (flags bits 0 and 2) instead of running for seconds; a row-count scan of the same
+    sketch with a short window that leaves it unsaturated still matches the oracle."""
+    import time
+    params = dict(q=12, r=6, delta=5, eta=8, qp=10, rp=2, etap=64, deltap=64, theta=8,
+                  anet_side=0, seed=43)
+    rng = np.random.default_rng(43)
+    g = sps.Sketch(params)
+    o = oracle.OracleSketch(params)
+    p = rng.integers(0, 1 << 32, size=(2_000_000, 2), dtype=np.uint64).astype(np.uint32)
+    g.ingest(dev_pkts(p), 1)
+    o.ingest(p, 1)
+    hot = o.hot(1)
+    assert hot.mean() > 0.99  # the oracle agrees the array is saturated
+    out = torch.zeros(4096 * 24, dtype=torch.uint8, device="cuda")
+    info = torch.zeros(8, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sps.sps_scan_async(g.h, 1, 8.0, out, 4096, info)
+    torch.cuda.synchronize()
+    assert time.perf_counter() - t0 < 2.0
+    f = int(info[sps.INFO_FLAGS].item())
+    assert f & 1 and f & 4 and int(info[sps.INFO_KEPT].item()) == 0
+    with pytest.raises(sps.SpsError) as e:
+        g.scan(1, 8.0)
+    assert e.value.code == sps.SPS_ECAPACITY
+    # a later, unsaturated window of the same sketch is searched as usual
+    q = rng.integers(0, 1 << 32, size=(3000, 2), dtype=np.uint64).astype(np.uint32)
+    g.ingest(dev_pkts(q), 2)
+    o.ingest(q, 2)
+    assert_scan_equal(g, o, 1, 8.0, "after saturation")
+    g.close()
