@@ -50,9 +50,12 @@ def make_backgrounds(params: dict, seed: int, n: int = 4) -> list:
 
 
 def generate(params: dict, n_hosts: int, seed: int, bases: list | None = None,
-             hosts_per_stream: int = 150, peer_budget: int = 16_000_000, log=None) -> Dataset:
+             hosts_per_stream: int = 150, peer_budget: int = 16_000_000, log=None,
+             law: int = 0) -> Dataset:
     """Hosts with log-uniform cardinalities embedded into background streams, ingested by the
-    GPU sketch; per-age features and linear-counting estimates read back per host."""
+    GPU sketch; per-age features and linear-counting estimates read back per host.  law: the
+    peers' arrival over the window (0: the training law; 1: fresh peers spread evenly over
+    the slices, as the scale workload's planted hosts)."""
     from synth import learned as L
 
     cards = L.draw_cards(seed, n_hosts)
@@ -71,7 +74,7 @@ def generate(params: dict, n_hosts: int, seed: int, bases: list | None = None,
             b += 1
         chunks.append((a, b))
         a = b
-    gen = L.PlantedGenerator(max(peer_budget, int(cards.max())) + 1)
+    gen = L.PlantedGenerator(max(peer_budget, int(cards.max())) + 1, law=law)
     work = sps.Sketch(params)
     feats = torch.zeros((n_hosts, WINDOW), dtype=torch.int32, device="cuda")
     res = torch.zeros(n_hosts * 24, dtype=torch.uint8, device="cuda")
@@ -174,7 +177,11 @@ def gated(ds: Dataset, y: np.ndarray, gate: Gate) -> tuple:
     in_range = np.all((f >= gate.lo) & (f <= gate.hi), axis=1)
     use = (ds.features[:, -1] >= gate.min_live) & in_range & informative(ds) & \
         (y >= 0) & (y <= math.log(gate.max_card))
-    return np.where(use, np.exp(y), ds.lc), use
+    net = np.exp(y.astype(np.float32)).astype(np.float64)
+    # a saturated linear count is the largest value it can express: the network only raises it
+    sat = (ds.lc_flags & sps.F_SATURATED) != 0
+    net = np.where(sat & (net < ds.lc), ds.lc, net)
+    return np.where(use, net, ds.lc), use
 
 
 def fit_gate(train_ds: Dataset, val: Dataset, y_val: np.ndarray, max_card: float = 1e6) -> Gate:

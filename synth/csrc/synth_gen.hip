@@ -2,10 +2,12 @@
 //
 // Input generation only (no arithmetic of the sketch method).  Host j of a stream has
 // card[j] distinct peers; peer i of host j is addr_mix(i + peer_salt[j]) (a bijection of i,
-// so peers of one host are distinct).  Every peer first appears in a slice f drawn
-// uniformly from 1..window and appears again in each later slice with probability 0.3.
-// Only its last appearance matters to a max-of-stamps sketch, so one packet (peer, host) is
-// written per peer, into the bucket of its last slice.
+// so peers of one host are distinct).  Arrival law 0: every peer first appears in a slice f
+// drawn uniformly from 1..window and appears again in each later slice with probability
+// 0.3.  Law 1 (the scale workload's planted hosts): the peers are fresh in every slice and
+// spread evenly, peer i appearing only in slice 1 + (i mod window).  Only its last
+// appearance matters to a max-of-stamps sketch, so one packet (peer, host) is written per
+// peer, into the bucket of its last slice.
 //
 // Randomness: rng(key, ctr) = SplitMix64 output number ctr + 1 from seed `key`
 // (Steele, Lea, Flood 2014), i.e. mix64(key + (ctr + 1) * 0x9E3779B97F4A7C15).
@@ -41,7 +43,7 @@ constexpr uint32_t kRepeat = 1288490189u;  // round(0.3 * 2^32)
 __global__ void __launch_bounds__(256) k_gen_planted(
     const uint32_t* __restrict__ host, const uint64_t* __restrict__ prefix,
     const uint32_t* __restrict__ peer_salt, uint32_t m, uint64_t key, uint32_t window,
-    uint32_t peer_domain_salt, uint32_t* __restrict__ out, uint64_t cap,
+    uint32_t peer_domain_salt, uint32_t law, uint32_t* __restrict__ out, uint64_t cap,
     unsigned long long* __restrict__ counts) {
   const uint64_t total = prefix[m];
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -60,12 +62,16 @@ __global__ void __launch_bounds__(256) k_gen_planted(
       const uint32_t i = (uint32_t)(g - prefix[lo]);
       src = addr_mix(i + peer_salt[lo], peer_domain_salt);
       dst = host[lo];
-      const uint32_t u = (uint32_t)(rng(key, g * 16) >> 32);
-      const uint32_t f = 1u + (uint32_t)(((uint64_t)u * window) >> 32);
-      uint32_t last = f;
-      for (uint32_t s = f + 1; s <= window; ++s)
-        if ((uint32_t)(rng(key, g * 16 + s) >> 32) < kRepeat) last = s;
-      bucket = last - 1;
+      if (law == 1) {
+        bucket = i % window;
+      } else {
+        const uint32_t u = (uint32_t)(rng(key, g * 16) >> 32);
+        const uint32_t f = 1u + (uint32_t)(((uint64_t)u * window) >> 32);
+        uint32_t last = f;
+        for (uint32_t s = f + 1; s <= window; ++s)
+          if ((uint32_t)(rng(key, g * 16 + s) >> 32) < kRepeat) last = s;
+        bucket = last - 1;
+      }
     }
     for (uint32_t b = 0; b < window; ++b) {
       const uint64_t mask = __ballot(bucket == b);
@@ -91,15 +97,16 @@ __global__ void __launch_bounds__(256) k_gen_planted(
 
 extern "C" int synth_gen_planted(const uint32_t* d_host, const uint64_t* d_prefix,
                                  const uint32_t* d_peer_salt, uint32_t m, uint64_t key,
-                                 uint32_t window, uint32_t peer_domain_salt, uint32_t* d_out,
-                                 uint64_t cap, unsigned long long* d_counts, void* stream) {
-  if (window < 1 || window > 15 || m == 0) return -1;
+                                 uint32_t window, uint32_t peer_domain_salt, uint32_t law,
+                                 uint32_t* d_out, uint64_t cap, unsigned long long* d_counts,
+                                 void* stream) {
+  if (window < 1 || window > 15 || m == 0 || law > 1) return -1;
   int dev = 0, n_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -6;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return -6;
   hipLaunchKernelGGL(k_gen_planted, dim3(n_cu * 8), dim3(256), 0, (hipStream_t)stream, d_host,
-                     d_prefix, d_peer_salt, m, key, window, peer_domain_salt, d_out, cap,
+                     d_prefix, d_peer_salt, m, key, window, peer_domain_salt, law, d_out, cap,
                      d_counts);
   return hipGetLastError() == hipSuccess ? 0 : -6;
 }

@@ -3,7 +3,10 @@
 Recipe (stands in for labelled traffic, which the paper does not have either):
   * cardinalities c = max(1, round(exp(U[0, ln c_max]))), log-uniform over 1..c_max;
   * every host's peers are distinct; a peer first appears in a slice drawn uniformly from the
-    window and appears again in every later slice with probability 0.3;
+    window and appears again in every later slice with probability 0.3 (arrival law 0, the
+    training law); law 1 -- the scale workload's planted hosts, for evaluation away from the
+    training law -- spreads fresh peers evenly over the slices, peer i only in slice
+    1 + (i mod window);
   * hosts are embedded a few hundred per stream into background streams of the scale
     workload's density (Zipf 1.05 over 2^22 hosts, 1,118,481 packets per slice);
   * a max-of-stamps sketch only keeps a peer's last appearance, so each peer contributes one
@@ -66,7 +69,7 @@ def background_recipe(seed: int) -> StreamRecipe:
                         n_hosts=1 << 22, zipf_s=1.05, planted=[])
 
 
-def planted_cpu(hosts, cards, salts, key: int, window: int = WINDOW):
+def planted_cpu(hosts, cards, salts, key: int, window: int = WINDOW, law: int = 0):
     """Numpy twin of the GPU generator: per-slice (n, 2) packet arrays, rows sorted."""
     cards = np.asarray(cards, dtype=np.int64)
     prefix = np.zeros(len(cards) + 1, dtype=np.int64)
@@ -77,12 +80,16 @@ def planted_cpu(hosts, cards, salts, key: int, window: int = WINDOW):
     with np.errstate(over="ignore"):
         src = addr_mix((i + salts[j]).astype(np.uint32), PEER_SALT)
     dst = np.asarray(hosts, dtype=np.uint32)[j]
-    u = (rng(key, g * np.uint64(16)) >> np.uint64(32)).astype(np.uint64)
-    f = (np.uint64(1) + ((u * np.uint64(window)) >> np.uint64(32))).astype(np.int64)
-    last = f.copy()
-    for s in range(2, window + 1):
-        hit = (rng(key, g * np.uint64(16) + np.uint64(s)) >> np.uint64(32)) < np.uint64(REPEAT)
-        last = np.where((s > f) & hit, s, last)
+    if law == 1:
+        last = 1 + (i.astype(np.int64) % window)
+    else:
+        u = (rng(key, g * np.uint64(16)) >> np.uint64(32)).astype(np.uint64)
+        f = (np.uint64(1) + ((u * np.uint64(window)) >> np.uint64(32))).astype(np.int64)
+        last = f.copy()
+        for s in range(2, window + 1):
+            hit = (rng(key, g * np.uint64(16) + np.uint64(s)) >> np.uint64(32)) < \
+                np.uint64(REPEAT)
+            last = np.where((s > f) & hit, s, last)
     out = []
     for s in range(1, window + 1):
         sel = last == s
@@ -115,7 +122,7 @@ def _glib():
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.synth_gen_planted.argtypes = [vp, vp, vp, C.c_uint32, C.c_uint64, C.c_uint32,
-                                        C.c_uint32, vp, C.c_uint64, vp, vp]
+                                        C.c_uint32, C.c_uint32, vp, C.c_uint64, vp, vp]
         L.synth_gen_planted.restype = C.c_int
         _lib = L
     return _lib
@@ -124,9 +131,10 @@ def _glib():
 class PlantedGenerator:
     """Generates one stream's planted packets on the GPU into per-slice buckets."""
 
-    def __init__(self, max_peers: int, window: int = WINDOW, device="cuda"):
+    def __init__(self, max_peers: int, window: int = WINDOW, device="cuda", law: int = 0):
         import torch
         self.window = window
+        self.law = law
         self.cap = int(max_peers)
         self.buf = torch.empty((window, self.cap, 2), dtype=torch.int32, device=device)
         self.counts = torch.zeros(window, dtype=torch.int64, device=device)
@@ -149,7 +157,7 @@ class PlantedGenerator:
         st = stream if stream is not None else torch.cuda.current_stream()
         rc = _glib().synth_gen_planted(
             C.c_void_p(h.data_ptr()), C.c_void_p(pf.data_ptr()), C.c_void_p(sl.data_ptr()),
-            len(cards), key, self.window, int(PEER_SALT), C.c_void_p(self.buf.data_ptr()),
+            len(cards), key, self.window, int(PEER_SALT), self.law, C.c_void_p(self.buf.data_ptr()),
             self.cap, C.c_void_p(self.counts.data_ptr()), C.c_void_p(st.cuda_stream))
         if rc:
             raise RuntimeError(f"synth_gen_planted: {rc}")

@@ -104,13 +104,14 @@ def test_adam_step_against_fp64():
         assert np.all(np.abs(a - omlp.flatten(want)) <= 1e-5 * scale + 1e-30)
 
 
-def test_generator_matches_cpu_twin():
+@pytest.mark.parametrize("law", [0, 1])
+def test_generator_matches_cpu_twin(law):
     from synth import learned as L
     cards = np.array([1, 7, 100, 3000, 20000, 5], dtype=np.int64)
     hosts = L.host_addrs(0, len(cards))
     salts = L.peer_salts(11, len(cards))
-    want = L.planted_cpu(hosts, cards, salts, key=1234)
-    gen = L.PlantedGenerator(int(cards.sum()) + 10)
+    want = L.planted_cpu(hosts, cards, salts, key=1234, law=law)
+    gen = L.PlantedGenerator(int(cards.sum()) + 10, law=law)
     got = gen.generate(hosts, cards, salts, key=1234)
     assert sum(len(b) for b in want) == cards.sum()
     for s in range(10):
@@ -176,3 +177,15 @@ def test_trained_network_beats_linear_counting():
     assert e_ml.mean() <= e_lc.mean()
     sat = (te.cards >= 8000) & (te.cards < 20000)
     assert e_ml[sat].mean() < e_lc[sat].mean()
+    # away from the training law: fresh peers spread evenly over the window (the scale
+    # workload's planted hosts); the gated network must not do worse than linear counting
+    ood = learned.generate(params, 20000, seed=0x5EED04, bases=bases, log=print, law=1)
+    est, use = learned.gated(ood, learned.predict(w, ood), gate)
+    o_lc = np.abs(ood.lc - ood.cards) / ood.cards
+    o_ml = np.abs(est - ood.cards) / ood.cards
+    for a, b in zip(learned.rel_err_table(ood.cards, ood.lc), learned.rel_err_table(ood.cards, est)):
+        print("even arrivals", a["decade"], a["n"], "LC", a["mean_rel_err"], "MLP", b["mean_rel_err"])
+    print("even arrivals: LC", o_lc.mean(), "MLP", o_ml.mean(), "used", use.mean())
+    assert o_ml.mean() <= o_lc.mean()
+    for b in bases:
+        b.close()
