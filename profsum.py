@@ -2,6 +2,7 @@
 
     python profsum.py stats  <kernel_stats.csv> <out.md> "<title>" "<command>"
     python profsum.py traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.md> "<commands>"
+    python profsum.py counters <out.md> "<title>" "<commands>" <pmc_dir> [<pmc_dir> ...]
 
 `traffic` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two --pmc runs of the same
 command) by what the same counters read for a plain 1 GiB device copy, writes a markdown table
@@ -56,8 +57,7 @@ def traffic(fd, wd, cfd, cwd, out, cmds):
             continue
         f = sum(fe[k]) / len(fe[k]) * kf * 1024
         w = sum(wr.get(k, [0.0])) / max(1, len(wr.get(k, []))) * kw * 1024
-        name = re.sub(r"<.*>", "", k)
-        js[name] = {"bytes_per_launch": int(f + w), "fetch_bytes": int(f), "write_bytes": int(w),
+        js[k] = {"bytes_per_launch": int(f + w), "fetch_bytes": int(f), "write_bytes": int(w),
                     "dispatches": len(fe[k]), "source_hash": h}
         table.append(f"| `{k}` | {len(fe[k])} | {f / 1e6:.2f} | {w / 1e6:.2f} | {(f + w) / 1e6:.2f} |")
     lines = ["# HBM traffic per launch, config-2 workload (rocprofv3 PMC)", "",
@@ -71,8 +71,50 @@ def traffic(fd, wd, cfd, cwd, out, cmds):
     json.dump(js, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
 
 
+def _counters_all(d):
+    """{kernel: {counter: [value per dispatch]}} from one --pmc run."""
+    f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    out = {}
+    for r in csv.DictReader(open(f)):
+        k = short(r["Kernel_Name"])
+        out.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def counters(out, title, cmds, *dirs):
+    """Per-kernel mean of every counter of several --pmc runs (one dispatch = one value per
+    counter), as a markdown table and as profiles/counters.json keyed by kernel with the
+    kernel-source hash they were taken on."""
+    sys.path.insert(0, ROOT)
+    from bench import kernel_source_hash
+    merged = {}
+    for d in dirs:
+        for k, cs in _counters_all(d).items():
+            for c, v in cs.items():
+                merged.setdefault(k, {})[c] = (sum(v) / len(v), len(v))
+    names = sorted({c for cs in merged.values() for c in cs})
+    h = kernel_source_hash()
+    lines = [f"# {title}", "", "Commands (repository root, one MI355X, ROCm 7.2):", "", "```",
+             cmds, "```", "", f"Kernel sources hash: `{h}`.  Values: mean per dispatch.", ""]
+    js = {}
+    for k in sorted(merged):
+        if not k.startswith("k_"):
+            continue
+        lines += [f"## `{k}`", "", "| counter | mean per dispatch | dispatches |", "|---|---|---|"]
+        for c in names:
+            if c in merged[k]:
+                m, n = merged[k][c]
+                lines.append(f"| {c} | {m:.4g} | {n} |")
+        lines.append("")
+        js[k] = {"counters": {c: merged[k][c][0] for c in merged[k]}, "source_hash": h}
+    open(out, "w").write("\n".join(lines) + "\n")
+    json.dump(js, open(os.path.join(ROOT, "profiles", "counters.json"), "w"), indent=1)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:6])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], *sys.argv[5:])
     else:
         traffic(*sys.argv[2:8])
