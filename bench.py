@@ -461,8 +461,9 @@ def main():
                     help="skip the merge (config 3), serving (config 4) and learned-estimator "
                          "(config 5) legs")
     ap.add_argument("--scan-overlap", type=int, default=0, choices=(0, 1, 2),
-                    help="1: row-count sweep on the sketch's side stream beside the candidate "
-                         "search; 2: everything on one stream; 0: the library's default")
+                    help="1: row-count sweep in waves of its own inside the candidate search's "
+                         "launch; 2: the sweep as a kernel of its own after the search; 0: the "
+                         "library's default")
     ap.add_argument("--tuning-cache", default="", metavar="JSON",
                     help="ingest launch shape from this tuning cache file when it holds the "
                          "workload's shape; otherwise autotune and write the file")
@@ -547,15 +548,20 @@ def main():
     if (inf[:, sps.INFO_FLAGS] != 0).any():
         raise RuntimeError("scan buffers overflowed")
     log(f"warm-up done; hosts reported per scan: {int(inf[:, 0].min())}..{int(inf[:, 0].max())}")
-    # one profiled step with every kernel bracketed: the breakdown and the dominant kernel
-    sps.sps_profile_enable(True)
+    # one profiled step with every kernel timed by its own dispatch (HIP events attached to
+    # the launch: no packets added to the stream): the breakdown and the dominant kernel; then
+    # one step with every whole scan bracketed by a pair of recorded events
+    kernel_stages = ("ingest", "scan_stats", "scan_rows", "join", "estimate", "sort", "fill")
+    sps.sps_profile_enable(True, stages=set(kernel_stages))
     sps.sps_profile_read()
     step()
     prof_all = sps.sps_profile_read()
-    kernel_stages = ("ingest", "scan_stats", "scan_rows", "join", "estimate", "sort", "fill")
+    sps.sps_profile_enable(True, stages={"scan"})
+    step()
+    prof_scan = sps.sps_profile_read()
     dominant = max(kernel_stages, key=lambda k: prof_all[k][0])
-    # timed region: events only around ingests, whole scans and the dominant kernel
-    sps.sps_profile_enable(True, stages={"ingest", "scan", dominant})
+    # timed region: the ingests and the dominant kernel, each timed by its own dispatch
+    sps.sps_profile_enable(True, stages={"ingest", dominant})
     sps.sps_profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -592,12 +598,13 @@ def main():
     tau, _, row_len = sk.derived()
     stores_per_pkt = params["rp"] + params["r"] * 2.0 ** -tau
     ingest_bytes_per_pkt = 8 + 2 * stores_per_pkt
-    # the row-count sweep streams the SLE array once (on the side stream, k_scan_rows); the
-    # hot-SRE pass streams the SRE array and writes the bitmap (k_scan_stats; with the sweep
-    # when there is no side stream)
+    # the row-count sweep streams the SLE array once (inside the candidate search's launch by
+    # default, else k_scan_rows); the hot-SRE pass (k_scan_sre) streams the SRE array and
+    # writes the hot bitmap and the join table
     rows_bytes = 2 * params["rp"] * row_len
-    sre_bytes = 2 * (params["r"] << params["q"]) * params["eta"] + (params["r"] << params["q"]) // 8
-    stats_bytes = sre_bytes + (0 if prof_all["scan_rows"][1] else rows_bytes)
+    n_sre = params["r"] << params["q"]
+    sre_bytes = 2 * n_sre * params["eta"] + n_sre // 8 + n_sre // 8
+    fused = sps.sps_get_scan_overlap(sk.h) and not prof_all["scan_rows"][1]
     # the candidate search: every expanded node tests its 2^delta extensions (Alg. 4-5), each
     # test a shift, xor, mask and bit test of 32-bit integers
     inf = info.cpu().numpy().astype(np.int64)
@@ -606,33 +613,42 @@ def main():
     join_ops = nodes_per_scan * (1 << params["delta"]) * JOIN_OPS_PER_TEST
     stage_ms = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                     "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
-                for k, v in prof_all.items() if v[1]}
-    kernel_names = {"ingest": "k_ingest<false, false>", "scan_stats": "k_scan_stats",
-                    "scan_rows": "k_scan_rows<false>", "join": "k_join<true>",
+                for k, v in list(prof_all.items()) + [("scan", prof_scan["scan"])] if v[1]}
+    kernel_names = {"ingest": "k_ingest<false, false>", "scan_stats": "k_scan_sre",
+                    "scan_rows": "k_scan_rows<false>",
+                    "join": "k_join<true, true>" if fused else "k_join<true, false>",
                     "estimate": "k_estimate", "sort": "k_rank_sort", "fill": "k_fill_zero"}
 
     hbm_bytes = {"ingest": rec.n_packets / rec.n_slices * ingest_bytes_per_pkt,
-                 "scan_stats": stats_bytes, "scan_rows": rows_bytes}
+                 "scan_stats": sre_bytes, "scan_rows": rows_bytes}
+    if fused:  # the search's launch also streams the SLE array
+        hbm_bytes["join"] = rows_bytes
+
+    def search_roofline(avg_s):
+        a = join_ops / avg_s / 1e12
+        out = {"bound": "alu", "achieved": round(a, 4), "peak": PEAK_INT32_TOPS,
+               "unit": "Tops/s (int32 lane ops)", "frac": round(a / PEAK_INT32_TOPS, 4),
+               "nodes_per_launch": int(nodes_per_scan), "alg_ops_per_launch": int(join_ops)}
+        # executed work: wave-level VALU instructions per launch (rocprofv3 SQ_INSTS_VALU,
+        # when taken on these kernel sources) against the issue rate of one wave64 VALU
+        # instruction per CU per clock
+        valu = stored_counter(kernel_names["join"], "SQ_INSTS_VALU")
+        if valu:
+            out["executed_valu_instr_per_launch"] = int(valu)
+            out["valu_issue_frac"] = round(valu / avg_s / PEAK_VALU_WAVE_INSTR, 4)
+        return out
 
     def kernel_roofline(stage, avg_s):
         if stage in hbm_bytes:
             b = hbm_bytes[stage]
             a = b / avg_s / 1e9
-            return {"bound": "hbm", "achieved": round(a, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(a / PEAK_HBM_GBS, 4), "alg_bytes_per_launch": int(b)}
-        if stage == "join":
-            a = join_ops / avg_s / 1e12
-            out = {"bound": "alu", "achieved": round(a, 4), "peak": PEAK_INT32_TOPS,
-                   "unit": "Tops/s (int32 lane ops)", "frac": round(a / PEAK_INT32_TOPS, 4),
-                   "nodes_per_launch": int(nodes_per_scan), "alg_ops_per_launch": int(join_ops)}
-            # executed work: wave-level VALU instructions per launch (rocprofv3 SQ_INSTS_VALU,
-            # when taken on these kernel sources) against the issue rate of one wave64 VALU
-            # instruction per CU per clock
-            valu = stored_counter("k_join<true>", "SQ_INSTS_VALU")
-            if valu:
-                out["executed_valu_instr_per_launch"] = int(valu)
-                out["valu_issue_frac"] = round(valu / avg_s / PEAK_VALU_WAVE_INSTR, 4)
+            out = {"bound": "hbm", "achieved": round(a, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": round(a / PEAK_HBM_GBS, 4), "alg_bytes_per_launch": int(b)}
+            if stage == "join":  # the search beside the sweep, against its own roof
+                out["search"] = search_roofline(avg_s)
             return out
+        if stage == "join":
+            return search_roofline(avg_s)
         return None
 
     avg_s = prof[dominant][0] / prof[dominant][1] / 1e3
@@ -669,7 +685,7 @@ def main():
         "ingest_tuning": tuning,
         "scan_overlap": sps.sps_get_scan_overlap(sk.h),
         "ingest_pkts_per_s": total_pkts / (prof["ingest"][0] / 1e3),
-        "scan_ms_per_slice": prof["scan"][0] / prof["scan"][1],
+        "scan_ms_per_slice": prof_scan["scan"][0] / prof_scan["scan"][1],
         "scan_ms_per_slice_median_with_d2h": scan_median_ms,
         "stage_ms_one_profiled_step": stage_ms,
         "per_kernel_roofline": per_kernel,

@@ -158,8 +158,10 @@ int sps_ingest_batched(sps_sketch* const* h_s, const sps_pkt* const* h_pkts, con
  * XCDs, so the recorders of one host are written through as few L2 caches as that allows.
  * Chosen by sps_autotune_ingest or set directly (0 keeps the current value).  Defaults:
  * 16 blocks per CU, tiles of 4096 pairs, 8 host classes.  scan_overlap (not tuned): 1 (the
- * default) runs a scan's sweep of the SLE array for the row live counts on the sketch's own
- * side stream, beside the candidate search; 2 runs everything on the scan's stream. */
+ * default) runs a scan's sweep of the SLE array for the row live counts in waves of its own
+ * inside the candidate search's launch, beside the search; 2 runs the sweep as a kernel of
+ * its own after the search.  Either way a scan is one stream of kernels on the caller's
+ * stream. */
 typedef struct sps_tuning {
   uint32_t blocks_per_cu;
   uint32_t batch_tile;
@@ -376,7 +378,7 @@ int sps_debug_copy(const sps_sketch* s, int which, void* h_buf, size_t bytes, si
 #define SPS_STAGE_MLP 11
 #define SPS_STAGE_SCAN 12
 #define SPS_STAGE_REBASE 13
-#define SPS_STAGE_SCAN_ROWS 14  /* the row-count sweep of a scan, on the sketch's side stream */
+#define SPS_STAGE_SCAN_ROWS 14  /* a scan's row-count sweep when it is a kernel of its own */
 #define SPS_NSTAGES 15
 int sps_profile_enable(uint32_t stage_mask);
 int sps_profile_read(double* h_ms, uint32_t* h_launches, int nstages);

@@ -40,7 +40,6 @@ struct sps_sketch {
   int n_cu;
   sps_tuning tune;
   bool hist_valid;        // dev.hist matches the SLE array (sliding mode; see k_ingest)
-  sps::ScanFork fork;     // side stream and events of the scans' row-count sweep
 };
 
 namespace {
@@ -257,22 +256,42 @@ int device_arch(int dev, char* out) {
 }  // namespace
 
 namespace sps {
-ProfScope::ProfScope(int stage, hipStream_t st) : stage_(stage), st_(st), ev0_(nullptr) {
+ProfScope::ProfScope(int stage, hipStream_t st, Kind kind)
+    : stage_(stage), st_(st), kind_(kind), ev0_(nullptr), ev1_(nullptr) {
   if (!((g_prof_mask.load(std::memory_order_relaxed) >> stage) & 1u)) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> g(g_prof_mu);
-  hipEvent_t e = prof_event();
-  if (e && hipEventRecord(e, st) == hipSuccess) ev0_ = e;
+  hipEvent_t a = prof_event();
+  if (!a) return;
+  if (kind == kKernel) {
+    hipEvent_t b = prof_event();
+    if (!b) {
+      g_prof_free.push_back(a);
+      return;
+    }
+    ev0_ = a;
+    ev1_ = b;
+  } else if (hipEventRecord(a, st) == hipSuccess) {
+    ev0_ = a;
+  } else {
+    g_prof_free.push_back(a);
+  }
 }
 ProfScope::~ProfScope() {
   if (!ev0_) return;
   std::lock_guard<std::mutex> g(g_prof_mu);
-  hipEvent_t e = prof_event();
-  if (e && hipEventRecord(e, st_) == hipSuccess)
-    g_prof_recs.push_back({stage_, static_cast<hipEvent_t>(ev0_), e});
-  else
-    g_prof_free.push_back(static_cast<hipEvent_t>(ev0_));
+  hipEvent_t a = static_cast<hipEvent_t>(ev0_);
+  hipEvent_t b = static_cast<hipEvent_t>(ev1_);
+  if (kind_ == kMarkers) {
+    b = prof_event();
+    if (!b || hipEventRecord(b, st_) != hipSuccess) {
+      if (b) g_prof_free.push_back(b);
+      g_prof_free.push_back(a);
+      return;
+    }
+  }
+  g_prof_recs.push_back({stage_, a, b});
 }
 }  // namespace sps
 
@@ -479,14 +498,9 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   s->tune.host_classes = 8;
   s->tune.scan_overlap = 1;
   s->hist_valid = p->row_counts != 0;  // all zero, like the state
-  s->fork = sps::ScanFork{nullptr, nullptr, nullptr};
   // zero state and workspace once, synchronously
   hipError_t e = hipMemset(s->base, 0, L.total);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  // the scans' side stream (default priority) and its fork/join events
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->fork.side, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork.ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork.ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     (void)sps_destroy(s);
     return hip_fail(e, "sps_create");
@@ -498,9 +512,6 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
 int sps_destroy(sps_sketch* s) {
   if (!s) return SPS_EINVAL;
   (void)hipDeviceSynchronize();
-  if (s->fork.ev_join) (void)hipEventDestroy(s->fork.ev_join);
-  if (s->fork.ev_fork) (void)hipEventDestroy(s->fork.ev_fork);
-  if (s->fork.side) (void)hipStreamDestroy(s->fork.side);
   if (s->owns) (void)hipFree(s->base);
   (void)hipHostFree(s->h_info);
 
@@ -890,9 +901,8 @@ int sps_scan_async(sps_sketch* s, uint32_t window, double threshold, sps_result*
   if (window < 1 || window > 65534u) return SPS_EINVAL;
   if (s->p.mode == SPS_MODE_DISCRETE && window != 1) return SPS_EINVAL;
   if (cap > 0xFFFFFFFFull) cap = 0xFFFFFFFFull;
-  const sps::ScanFork none{nullptr, nullptr, nullptr};
   SPS_HIP(sps::launch_scan(s->dev, s->cur, window, threshold, d_out, (uint32_t)cap, d_info,
-                           s->mlp, s->hist_valid, s->tune.scan_overlap == 1 ? s->fork : none, s->n_cu,
+                           s->mlp, s->hist_valid, s->tune.scan_overlap, s->n_cu,
                            (hipStream_t)stream));
   return SPS_OK;
 }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "sps.h"
@@ -59,8 +60,8 @@ struct Dev {
   sps_result* kept;       // [cand_cap] kept hosts, unordered
   uint64_t* skeys;        // [cand_cap] (host << 32 | index into kept), sorted per 4096-tile
   Ctrl* ctrl;
-  uint32_t* rows_part;    // [kMaxRP][kRowsPartWaves] per-wave row live counts of the sweep
-                          // that runs on a scan's side stream (summed by the estimate)
+  uint32_t* rows_part;    // [kMaxRP][kRowsPartWaves] partial row live counts of a scan's
+                          // sweep, per block or per wave (summed by the estimate)
   uint32_t* hist;         // [r'][kHistBins] per-row stamp histograms: hist[i][v] = cells of
                           // SLE-array row i whose stamp is v (v >= 1; bin 0 unused)
   uint64_t row_len;       // L' = 2^q' delta' + eta' - delta'
@@ -94,17 +95,36 @@ __device__ __forceinline__ float mlp_encode(uint32_t x, uint32_t etap) {
   return log1pf(-(float)etap * log1pf(-u)) * 0.125f;
 }
 
-// Stage timing (sps_api.hip): brackets one launch with HIP events while profiling is on.
+// Stage timing (sps_api.hip), while profiling is on and the stream is not being captured.
+// A marker scope brackets whatever it encloses with two recorded events.  A kernel scope
+// records nothing itself: its two events go to the one launch it encloses (launch_k), which
+// sets them from the kernel's own start and end, so timing adds no packets to the stream.
 class ProfScope {
  public:
-  ProfScope(int stage, hipStream_t st);
+  enum Kind { kMarkers, kKernel };
+  ProfScope(int stage, hipStream_t st, Kind kind = kMarkers);
   ~ProfScope();
+  bool kernel_timed() const { return kind_ == kKernel && ev0_ != nullptr; }
+  hipEvent_t start() const { return static_cast<hipEvent_t>(ev0_); }
+  hipEvent_t stop() const { return static_cast<hipEvent_t>(ev1_); }
 
  private:
   int stage_;
   hipStream_t st_;
+  Kind kind_;
   void* ev0_;
+  void* ev1_;
 };
+
+// One launch, timed by its own dispatch when `ps` is a timed kernel scope.
+template <typename F, typename... Args>
+inline void launch_k(const ProfScope& ps, F kernel, dim3 grid, dim3 block, uint32_t lds,
+                     hipStream_t st, Args... args) {
+  if (ps.kernel_timed())
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, st, ps.start(), ps.stop(), 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
 
 // Launchers (sps_kernels.hip).
 // track: keep d.hist exact (SLE cells set by compare-and-swap, each stamp change counted)
@@ -133,16 +153,13 @@ hipError_t launch_hist_rebase(uint32_t* hist, uint32_t rows, uint32_t offset, hi
 hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsrc,
                         uint64_t bytes, bool bits, hipStream_t st);
 hipError_t prepare_join();  // allows the join its LDS (call before the first scan)
-// Side stream of a scan: the row-count sweep runs there beside the candidate search (side
-// null: everything on the scan's stream).  The two events are the fork and the join.
-struct ScanFork {
-  hipStream_t side;
-  hipEvent_t ev_fork, ev_join;
-};
+// Where a scan's row-count sweep runs: in waves of its own inside the candidate search's
+// launch, or as a kernel of its own after the search.
+enum ScanMode : uint32_t { kScanFused = 1, kScanSerial = 2 };
 // use_hist: row live counts from d.hist instead of a sweep of the SLE array
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       bool use_hist, const ScanFork& fork, int n_cu, hipStream_t st);
+                       bool use_hist, uint32_t mode, int n_cu, hipStream_t st);
 // Region offsets of the replay probe's cell list, one region per host class (XCD).
 struct ClassOffsets {
   uint64_t off[9];

@@ -214,16 +214,16 @@ hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t
   uint64_t b = (uint64_t)blocks / n_cls * n_cls;
   if (b > need * n_cls) b = need * n_cls;
   if (b < n_cls) b = n_cls;
-  ProfScope ps(SPS_STAGE_INGEST, st);
+  ProfScope ps(SPS_STAGE_INGEST, st, ProfScope::kKernel);
   const u32x2* p2 = reinterpret_cast<const u32x2*>(pkts);
   if (d.mode == SPS_MODE_DISCRETE)
-    hipLaunchKernelGGL((k_ingest<false, true>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
+    launch_k(ps, (k_ingest<false, true>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
                        n, stamp, n_cls);
   else if (track)
-    hipLaunchKernelGGL((k_ingest<true, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
+    launch_k(ps, (k_ingest<true, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
                        n, stamp, n_cls);
   else
-    hipLaunchKernelGGL((k_ingest<false, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
+    launch_k(ps, (k_ingest<false, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
                        n, stamp, n_cls);
   return hipGetLastError();
 }
@@ -285,15 +285,15 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
   uint64_t b = (uint64_t)blocks / n_cls * n_cls;
   if (b > total * n_cls) b = total * n_cls;
   if (b < n_cls) b = n_cls;
-  ProfScope ps(SPS_STAGE_INGEST_BATCHED, st);
+  ProfScope ps(SPS_STAGE_INGEST_BATCHED, st, ProfScope::kKernel);
   if (shape.mode == SPS_MODE_DISCRETE)
-    hipLaunchKernelGGL((k_ingest_batched<false, true>), dim3((uint32_t)b), dim3(threads), 0, st,
+    launch_k(ps, (k_ingest_batched<false, true>), dim3((uint32_t)b), dim3(threads), 0, st,
                        shape, t, m, tile, stamp, n_cls);
   else if (track)
-    hipLaunchKernelGGL((k_ingest_batched<true, false>), dim3((uint32_t)b), dim3(threads), 0, st,
+    launch_k(ps, (k_ingest_batched<true, false>), dim3((uint32_t)b), dim3(threads), 0, st,
                        shape, t, m, tile, stamp, n_cls);
   else
-    hipLaunchKernelGGL((k_ingest_batched<false, false>), dim3((uint32_t)b), dim3(threads), 0, st,
+    launch_k(ps, (k_ingest_batched<false, false>), dim3((uint32_t)b), dim3(threads), 0, st,
                        shape, t, m, tile, stamp, n_cls);
   return hipGetLastError();
 }
@@ -313,8 +313,8 @@ hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st) {
   if (nvec == 0) return hipSuccess;
   uint64_t blocks = (nvec + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  ProfScope ps(SPS_STAGE_FILL, st);
-  hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st,
+  ProfScope ps(SPS_STAGE_FILL, st, ProfScope::kKernel);
+  launch_k(ps, k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st,
                      reinterpret_cast<u32x4*>(p), nvec);
   return hipGetLastError();
 }
@@ -352,8 +352,8 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
     MergeSrcs s{};
     const uint32_t k = nsrc - b < (uint32_t)kMaxMerge ? nsrc - b : (uint32_t)kMaxMerge;
     for (uint32_t j = 0; j < k; ++j) s.p[j] = reinterpret_cast<const u16x8*>(srcs[b + j]);
-    ProfScope ps(SPS_STAGE_MERGE, st);
-    hipLaunchKernelGGL(k_merge_max, dim3((uint32_t)blocks), dim3(256), 0, st,
+    ProfScope ps(SPS_STAGE_MERGE, st, ProfScope::kKernel);
+    launch_k(ps, k_merge_max, dim3((uint32_t)blocks), dim3(256), 0, st,
                        reinterpret_cast<u16x8*>(dst), s, k, nvec, bits ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -378,8 +378,8 @@ hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream
   if (nvec == 0 || offset == 0) return hipSuccess;
   uint64_t blocks = (nvec + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  ProfScope ps(SPS_STAGE_REBASE, st);
-  hipLaunchKernelGGL(k_rebase, dim3((uint32_t)blocks), dim3(256), 0, st,
+  ProfScope ps(SPS_STAGE_REBASE, st, ProfScope::kKernel);
+  launch_k(ps, k_rebase, dim3((uint32_t)blocks), dim3(256), 0, st,
                      reinterpret_cast<u16x8*>(p), nvec, offset);
   return hipGetLastError();
 }
@@ -402,8 +402,8 @@ __global__ void __launch_bounds__(256) k_hist_rebase(uint32_t* __restrict__ hist
 
 hipError_t launch_hist_rebase(uint32_t* hist, uint32_t rows, uint32_t offset, hipStream_t st) {
   if (offset == 0 || rows == 0) return hipSuccess;
-  ProfScope ps(SPS_STAGE_REBASE, st);
-  hipLaunchKernelGGL(k_hist_rebase, dim3(rows), dim3(256), 0, st, hist, offset);
+  ProfScope ps(SPS_STAGE_REBASE, st, ProfScope::kKernel);
+  launch_k(ps, k_hist_rebase, dim3(rows), dim3(256), 0, st, hist, offset);
   return hipGetLastError();
 }
 
@@ -424,8 +424,8 @@ hipError_t launch_scan_reset(const Dev& d, bool with_table, hipStream_t st) {
   uint32_t blocks = (words + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
-  ProfScope ps(SPS_STAGE_SCAN_RESET, st);
-  hipLaunchKernelGGL(k_scan_reset, dim3(blocks), dim3(256), 0, st, d.ctrl, d.hot_t, words);
+  ProfScope ps(SPS_STAGE_SCAN_RESET, st, ProfScope::kKernel);
+  launch_k(ps, k_scan_reset, dim3(blocks), dim3(256), 0, st, d.ctrl, d.hot_t, words);
   return hipGetLastError();
 }
 
@@ -459,8 +459,8 @@ __device__ __forceinline__ uint32_t live8_pairs(u32x4 v, uint32_t lom1, uint32_t
          live_pairs(v.z, lom1, ones) + live_pairs(v.w, lom1, ones);
 }
 
-// One SRE per lane (64 consecutive SREs per wave): k-weight >= hot cut marks it hot.
-__device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sre_idx) {
+// k-weight of one SRE (Sec. 3.3): its live cells, or its set bits in the discrete variant.
+__device__ __forceinline__ uint32_t sre_weight(const Dev& d, uint32_t lo, uint64_t sre_idx) {
   uint32_t w = 0;
   if (d.mode == SPS_MODE_DISCRETE) {  // eta bits per SRE: eta / 8 bytes
     const uint8_t* by = reinterpret_cast<const uint8_t*>(d.sre) + (sre_idx * d.eta >> 3);
@@ -469,7 +469,12 @@ __device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sr
     const u32x4* cell = reinterpret_cast<const u32x4*>(d.sre + (sre_idx << __builtin_ctz(d.eta)));
     for (uint32_t v = 0; v < d.eta / 8; ++v) w += live8(cell[v], lo);
   }
-  const bool hot = w >= d.hot_cut;
+  return w;
+}
+
+// One SRE per lane (64 consecutive SREs per wave): k-weight >= hot cut marks it hot.
+__device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sre_idx) {
+  const bool hot = sre_weight(d, lo, sre_idx) >= d.hot_cut;
   const uint64_t mask = __ballot(hot);
   const uint32_t row = (uint32_t)(sre_idx >> d.q);
   const uint32_t col = (uint32_t)(sre_idx & ((1u << d.q) - 1u));
@@ -497,17 +502,133 @@ __device__ __forceinline__ void sre_group(const Dev& d, uint32_t lo, uint64_t sr
   }
 }
 
-// Stage 1.  All blocks stream the SLE array as one flat range (grid-stride with eight 16-byte
-// non-temporal loads in flight per lane), so all blocks carry equal work, and add their
-// per-row live-cell counts to row_live (Def. 4); then (with_sre) the same waves take the
-// SREs 64 at a time.  The
-// remaining blocks take one SRE per lane: k-weight >= hot cut marks it hot (Sec. 3.3); a
-// wave's 64 verdicts become one ballot word of the hot bitmap, and rows 0 and 1 also append
-// their hot columns to the HSE lists.
+// Stage 1: the row live counts (Def. 4 numerators) and the hot SREs (Sec. 3.3).
+//
+// Row live counts come from one of three places: the stamp histograms (a few hundred bins per
+// row), a sweep of the SLE array run inside the candidate search's launch, or a sweep run as a
+// kernel of its own.  A sweep streams the rows as one flat range (grid-stride with eight
+// 16-byte non-temporal loads in flight per lane and the next eight issued before the current
+// ones are counted), so all lanes carry equal work.
+//
+// Hot SREs: a wave takes 64 SREs, one per lane; k-weight >= hot cut marks it hot.  The 64
+// verdicts become two words of the hot bitmap, rows 0 and 1 append their hot columns to the
+// HSE lists, and every hot SRE sets its bit of the join's table.
 constexpr uint32_t kStatsSre = 1u;   // the SREs (hot bitmap, lists, join table, row counts)
 constexpr uint32_t kStatsHist = 2u;  // row live counts from the stamp histograms
 constexpr uint32_t kStatsRows = 4u;  // row live counts (histograms, else a sweep)
 constexpr uint32_t kStatsPartials = 8u;  // the sweep leaves per-wave counts in d.rows_part
+
+// Row b's live cells from its histogram: the bins lo..hi (one block; added to row_live).
+__device__ __forceinline__ void hist_row_live(const Dev& d, uint32_t b, uint32_t lo,
+                                              uint32_t hi) {
+  __shared__ uint32_t red[1024 / kWave];
+  const uint32_t* h = d.hist + (uint64_t)b * kHistBins;
+  uint32_t c = 0;
+  for (uint32_t v = lo + threadIdx.x; v <= hi; v += blockDim.x) c += h[v];
+  c = wave_sum(c);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[w];
+    atomicAdd(&d.ctrl->row_live[b], t);
+  }
+}
+
+// 16-byte loads a sweep lane keeps in one batch (two batches in flight).
+constexpr int kSweepBatch = 8;
+
+// One lane's share of a sweep of `step` lanes (this one is lane `first`): its live cells of
+// every row, added to cnt[row].
+__device__ __forceinline__ void sweep_lane(const Dev& d, uint32_t lo, uint64_t first,
+                                           uint64_t step, uint32_t (&cnt)[kMaxRP]) {
+  auto add_to = [&cnt](uint32_t row, uint32_t c) {
+#pragma unroll
+    for (int j = 0; j < kMaxRP; ++j)
+      if ((uint32_t)j == row) cnt[j] += c;
+  };
+  if (d.mode == SPS_MODE_DISCRETE) {  // one bit per cell: a row is row_stride / 128 vectors
+    for (uint32_t row = 0; row < d.rp; ++row) {
+      const u32x4* rowb = reinterpret_cast<const u32x4*>(
+          reinterpret_cast<const uint32_t*>(d.slea) + (uint64_t)row * (d.row_stride >> 5));
+      const uint64_t nvb = d.row_stride >> 7;
+      uint32_t c = 0;
+      for (uint64_t v = first; v < nvb; v += step) {
+        const u32x4 a = __builtin_nontemporal_load(&rowb[v]);
+        c += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
+      }
+      add_to(row, c);
+    }
+    return;
+  }
+  // the rows are one flat range: the sweep runs across row ends without draining, and a
+  // lane's counts move to the next row when its index passes a row boundary
+  const u32x4* vec = reinterpret_cast<const u32x4*>(d.slea);
+  const uint64_t nvec = d.row_stride / 8, total = (uint64_t)d.rp * nvec;
+  uint32_t row = (uint32_t)(first / nvec);
+  uint64_t next_b = (uint64_t)(row + 1u) * nvec;  // first vector of the next row
+  uint32_t acc = 0;
+  auto account = [&](uint64_t idx, uint32_t c) {
+    while (idx >= next_b) {
+      add_to(row, acc);
+      acc = 0;
+      ++row;
+      next_b += nvec;
+    }
+    acc += c;
+  };
+  const uint32_t lom1 = (lo - 1u) * 0x10001u, ones = 0x10001u;
+  // two batches of kSweepBatch loads, the next issued before the current one is counted; load
+  // indices are clamped into the array so the batches are unconditional
+  constexpr int N = kSweepBatch;
+  auto load_batch = [&](u32x4* a, uint64_t v0) {
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const uint64_t j = v0 + u * step;
+      a[u] = __builtin_nontemporal_load(&vec[j < total ? j : total - 1]);
+    }
+  };
+  auto count_batch = [&](const u32x4* a, uint64_t v0) {
+    if (v0 + (N - 1) * step < next_b) {  // all of the batch in the current row
+      uint32_t pr = 0;  // packed counts, at most 4 N per half
+#pragma unroll
+      for (int u = 0; u < N; ++u) pr += live8_pairs(a[u], lom1, ones);
+      acc += (pr & 0xFFFFu) + (pr >> 16);
+    } else {
+#pragma unroll
+      for (int u = 0; u < N; ++u) account(v0 + u * step, live8(a[u], lo));
+    }
+  };
+  uint64_t v = first;
+  u32x4 A[N], B[N];
+  load_batch(A, v);
+  for (;;) {
+    if (v + (N - 1) * step >= total) break;
+    load_batch(B, v + N * step);
+    count_batch(A, v);
+    v += N * step;
+    if (v + (N - 1) * step >= total) break;
+    load_batch(A, v + N * step);
+    count_batch(B, v);
+    v += N * step;
+  }
+  for (; v < total; v += step) account(v, live8(__builtin_nontemporal_load(&vec[v]), lo));
+  add_to(row, acc);
+}
+
+// A wave's sweep counts as one plain store per row into the partials (wave gw of the sweep),
+// summed by the estimate: no LDS and no same-address atomics at the end of the sweep.
+__device__ __forceinline__ void sweep_partials(const Dev& d, const uint32_t (&cnt)[kMaxRP],
+                                               uint32_t gw) {
+  for (uint32_t j = 0; j < d.rp; ++j) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int jj = 0; jj < kMaxRP; ++jj)
+      if ((uint32_t)jj == j) c = cnt[jj];
+    c = wave_sum(c);
+    if (lane_id() == 0) d.rows_part[(uint64_t)j * kRowsPartWaves + gw] = c;
+  }
+}
 
 __device__ __forceinline__ void scan_stats_body(const Dev& d, uint32_t lo, uint32_t hi,
                                                 uint32_t flags) {
@@ -515,110 +636,15 @@ __device__ __forceinline__ void scan_stats_body(const Dev& d, uint32_t lo, uint3
   const uint32_t b = blockIdx.x;
   const bool with_sre = (flags & kStatsSre) != 0u;
   if ((flags & kStatsRows) && (flags & kStatsHist)) {
-    // row b's live cells: the stamps lo..hi of its histogram (Def. 4 numerator)
-    if (b < d.rp) {
-      const uint32_t* h = d.hist + (uint64_t)b * kHistBins;
-      uint32_t c = 0;
-      for (uint32_t v = lo + threadIdx.x; v <= hi; v += blockDim.x) c += h[v];
-      c = wave_sum(c);
-      if (lane_id() == 0) red[0][threadIdx.x / kWave] = c;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[0][w];
-        atomicAdd(&d.ctrl->row_live[b], t);
-      }
-    }
+    if (b < d.rp) hist_row_live(d, b, lo, hi);
   } else if (flags & kStatsRows) {
-    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t first = (uint64_t)b * blockDim.x + threadIdx.x;
     uint32_t cnt[kMaxRP];
 #pragma unroll
     for (int j = 0; j < kMaxRP; ++j) cnt[j] = 0;
-    auto add_to = [&cnt](uint32_t row, uint32_t c) {
-#pragma unroll
-      for (int j = 0; j < kMaxRP; ++j)
-        if ((uint32_t)j == row) cnt[j] += c;
-    };
-    if (d.mode == SPS_MODE_DISCRETE) {  // one bit per cell: a row is row_stride / 128 vectors
-      for (uint32_t row = 0; row < d.rp; ++row) {
-        const u32x4* rowb = reinterpret_cast<const u32x4*>(
-            reinterpret_cast<const uint32_t*>(d.slea) + (uint64_t)row * (d.row_stride >> 5));
-        const uint64_t nvb = d.row_stride >> 7;
-        uint32_t c = 0;
-        for (uint64_t v = first; v < nvb; v += step) {
-          const u32x4 a = __builtin_nontemporal_load(&rowb[v]);
-          c += __popc(a.x) + __popc(a.y) + __popc(a.z) + __popc(a.w);
-        }
-        add_to(row, c);
-      }
-    } else {
-      // the rows are one flat range: the sweep runs across row ends without draining, and a
-      // lane's counts move to the next row when its index passes a row boundary
-      const u32x4* vec = reinterpret_cast<const u32x4*>(d.slea);
-      const uint64_t nvec = d.row_stride / 8, total = (uint64_t)d.rp * nvec;
-      uint32_t row = (uint32_t)(first / nvec);
-      uint64_t next_b = (uint64_t)(row + 1u) * nvec;  // first vector of the next row
-      uint32_t acc = 0;
-      auto account = [&](uint64_t idx, uint32_t c) {
-        while (idx >= next_b) {
-          add_to(row, acc);
-          acc = 0;
-          ++row;
-          next_b += nvec;
-        }
-        acc += c;
-      };
-      const uint32_t lom1 = (lo - 1u) * 0x10001u, ones = 0x10001u;
-      // two batches of eight loads, the next issued before the current one is counted; load
-      // indices are clamped into the array so the batches are unconditional
-      auto load8 = [&](u32x4* a, uint64_t v0) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const uint64_t j = v0 + u * step;
-          a[u] = __builtin_nontemporal_load(&vec[j < total ? j : total - 1]);
-        }
-      };
-      auto count8 = [&](const u32x4* a, uint64_t v0) {
-        if (v0 + 7 * step < next_b) {  // all eight in the current row
-          uint32_t pr = 0;  // packed counts, at most 32 per half
-#pragma unroll
-          for (int u = 0; u < 8; ++u) pr += live8_pairs(a[u], lom1, ones);
-          acc += (pr & 0xFFFFu) + (pr >> 16);
-        } else {
-#pragma unroll
-          for (int u = 0; u < 8; ++u) account(v0 + u * step, live8(a[u], lo));
-        }
-      };
-      uint64_t v = first;
-      u32x4 A[8], B[8];
-      load8(A, v);
-      for (;;) {
-        if (v + 7 * step >= total) break;
-        load8(B, v + 8 * step);
-        count8(A, v);
-        v += 8 * step;
-        if (v + 7 * step >= total) break;
-        load8(A, v + 8 * step);
-        count8(B, v);
-        v += 8 * step;
-      }
-      for (; v < total; v += step) account(v, live8(__builtin_nontemporal_load(&vec[v]), lo));
-      add_to(row, acc);
-    }
+    sweep_lane(d, lo, (uint64_t)b * blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x,
+               cnt);
     if (flags & kStatsPartials) {
-      // one plain store per wave and row, summed later by the estimate: no LDS (so these
-      // blocks fit on a compute unit beside the candidate search's block, which takes nearly
-      // all of it) and no same-address atomics at the end of the sweep
-      const uint32_t gw = b * (blockDim.x / kWave) + threadIdx.x / kWave;
-      for (uint32_t j = 0; j < d.rp; ++j) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int jj = 0; jj < kMaxRP; ++jj)
-          if ((uint32_t)jj == j) c = cnt[jj];
-        c = wave_sum(c);
-        if (lane_id() == 0) d.rows_part[(uint64_t)j * kRowsPartWaves + gw] = c;
-      }
+      sweep_partials(d, cnt, b * (blockDim.x / kWave) + threadIdx.x / kWave);
     } else {
       for (uint32_t j = 0; j < d.rp; ++j) {
         uint32_t c = 0;
@@ -645,35 +671,82 @@ __device__ __forceinline__ void scan_stats_body(const Dev& d, uint32_t lo, uint3
     sre_group(d, lo, g * kWave + lane_id());
 }
 
-// The hot-SRE pass (and, with kStatsRows, the row live counts first).
+// The row live counts and/or the hot SREs one SRE per lane, the join table by atomic ORs.
 __global__ void __launch_bounds__(256) k_scan_stats(Dev d, uint32_t lo, uint32_t hi,
                                                     uint32_t flags) {
   scan_stats_body(d, lo, hi, flags);
 }
 
-// The row live counts alone, as per-wave partial counts: the sweep that runs on a scan's side
-// stream; k_rows_sum then adds up the partials.
+// The hot SREs by tiles (for q - delta >= 6).  A tile is one row's 64 consecutive low parts
+// (the column's q - delta low bits) with all 2^delta top parts: 2^(delta+6) SREs whose bits
+// of the join's table (position (low << delta) + top within the row) fill 2^(delta+1) whole
+// words.  A block owns its tiles' words of the hot bitmap and of the table, so both take
+// plain stores, and a tile's hot count and (rows 0 and 1) its place in the HSE list take one
+// atomic each.  With `hist` the first r' blocks first take the row live counts from the
+// histograms.
+__global__ void __launch_bounds__(256) k_scan_sre(Dev d, uint32_t lo, uint32_t hi,
+                                                  uint32_t hist) {
+  __shared__ unsigned long long gm[1u << 5];  // hot masks of the tile's groups (delta <= 5)
+  __shared__ uint32_t pre[(1u << 5) + 1u];    // hot SREs of the groups before each one
+  __shared__ uint32_t base_sh;
+  if (hist && blockIdx.x < d.rp) {
+    hist_row_live(d, blockIdx.x, lo, hi);
+    __syncthreads();
+  }
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t lane = lane_id(), nw = blockDim.x / kWave;
+  const uint32_t lowbits = d.q - d.delta, groups = 1u << d.delta;
+  const uint32_t tiles_row = 1u << (lowbits - 6u);
+  const uint32_t n_tiles = d.r << (lowbits - 6u);
+  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint32_t row = tile >> (lowbits - 6u);
+    const uint32_t l0 = (tile & (tiles_row - 1u)) << 6;
+    const uint64_t row0 = (uint64_t)row << d.q;
+    for (uint32_t t = wave; t < groups; t += nw) {
+      const uint64_t first = row0 + l0 + (t << lowbits);  // a multiple of 64
+      const bool hot = sre_weight(d, lo, first + lane) >= d.hot_cut;
+      const uint64_t mask = __ballot(hot);
+      if (lane < 2u) d.hot[(first >> 5) + lane] = (uint32_t)(mask >> (32u * lane));
+      if (lane == 0u) gm[t] = mask;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t s = 0;
+      for (uint32_t t = 0; t < groups; ++t) {
+        pre[t] = s;
+        s += (uint32_t)__popcll(gm[t]);
+      }
+      if (s) atomicAdd(&d.ctrl->hot_rows[row], s);
+      base_sh = (row < 2u && s) ? atomicAdd(&d.ctrl->hse_count[row], s) : 0u;
+    }
+    // bit b of the tile's table word j is position p = 32 j + b = (low offset << delta) + top
+    if (threadIdx.x < (2u << d.delta)) {
+      uint32_t v = 0;
+      for (uint32_t b = 0; b < 32u; ++b) {
+        const uint32_t p = threadIdx.x * 32u + b;
+        v |= (uint32_t)((gm[p & (groups - 1u)] >> (p >> d.delta)) & 1ull) << b;
+      }
+      d.hot_t[((row0 + ((uint64_t)l0 << d.delta)) >> 5) + threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (row < 2u) {
+      for (uint32_t t = wave; t < groups; t += nw) {
+        const uint64_t m = gm[t];
+        if ((m >> lane) & 1ull) {
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          d.hse[row0 + base_sh + pre[t] + below] = l0 + lane + (t << lowbits);
+        }
+      }
+    }
+    __syncthreads();  // gm, pre and base_sh are rewritten by the next tile
+  }
+}
+
+// The row live counts alone, as per-wave partial counts, in a launch of its own.
 template <bool kBits>  // a separate symbol for the discrete variant's sweep of bits
 __global__ void __launch_bounds__(256) k_scan_rows(Dev d, uint32_t lo, uint32_t hi) {
   scan_stats_body(d, lo, hi, kStatsRows | kStatsPartials);
-}
-
-// One block: the row live counts from the sweep's `waves` per-wave partials.
-__global__ void __launch_bounds__(256) k_rows_sum(Dev d, uint32_t waves) {
-  __shared__ uint32_t red[kMaxRP][256 / kWave];
-  for (uint32_t j = 0; j < d.rp; ++j) {
-    uint32_t c = 0;
-    for (uint32_t w = threadIdx.x; w < waves; w += blockDim.x)
-      c += d.rows_part[(uint64_t)j * kRowsPartWaves + w];
-    c = wave_sum(c);
-    if (lane_id() == 0) red[j][threadIdx.x / kWave] = c;
-  }
-  __syncthreads();
-  if (threadIdx.x < d.rp) {
-    uint32_t t = 0;
-    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
-    d.ctrl->row_live[threadIdx.x] = t;
-  }
 }
 
 // Hot extensions of a node (Alg. 4-5 check, in bulk).  Row i's SRE for the extension t is
@@ -1187,28 +1260,64 @@ __device__ double join_expected_nodes(const Dev& d) {
 // not run and the scan reports a candidate overflow instead of running for minutes.
 constexpr double kJoinNodeBudget = 68719476736.0;
 
-template <bool kTbLds>
+// The block's first `jw` waves search; with kSweep the others sweep the SLE array for the row
+// live counts meanwhile (one lane of the sweep each, partial counts per wave), so the
+// HBM-bound sweep runs beside the ALU-bound search in the same launch.  Sweep waves take part
+// in the block's barriers and leave the stacks, lists and candidate buffer alone.
+template <bool kTbLds, bool kSweep>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
-                                                          uint32_t list_words) {
+                                                          uint32_t list_words, uint32_t jw,
+                                                          uint32_t lo) {
   extern __shared__ uint32_t sh[];
   const uint32_t q = d.q, r = d.r;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const bool sweeper = kSweep && wave >= jw;
+  const uint32_t off = kTbLds ? (r << q) >> 5 : 0u;  // words of the table in LDS (even)
+  // stacks for the search waves only (a sweep wave's pointer is never used)
+  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)wave * cap;
+  uint32_t* const lw = sh + off + 2u * cap * jw;
+  // [count, base, next group, -, kCandBuf entries, sweep counts (kMaxRP per sweep wave)]
+  uint32_t* const sink = lw + list_words;
+  uint32_t* const swc = sink + 4u + kCandBuf;
+  // a sweep wave's share of the sweep: its per-row counts into the LDS
+  auto sweep = [&]() {
+    __builtin_amdgcn_s_setprio(2);  // ahead of the search's waves for issue
+    const uint32_t sw = blockDim.x / kWave - jw;
+    const uint32_t gw = blockIdx.x * sw + (wave - jw);
+    uint32_t cnt[kMaxRP];
+#pragma unroll
+    for (int j = 0; j < kMaxRP; ++j) cnt[j] = 0;
+    sweep_lane(d, lo, (uint64_t)gw * kWave + lane_id(), (uint64_t)gridDim.x * sw * kWave, cnt);
+#pragma unroll
+    for (int j = 0; j < kMaxRP; ++j) {
+      const uint32_t c = wave_sum(cnt[j]);
+      if (lane_id() == 0) swc[(wave - jw) * kMaxRP + j] = c;
+    }
+  };
+  // after a barrier: the block's counts, one partial per block and row
+  auto sweep_store = [&]() {
+    if (kSweep && threadIdx.x < d.rp) {
+      uint32_t t = 0;
+      for (uint32_t w = 0; w < blockDim.x / kWave - jw; ++w) t += swc[w * kMaxRP + threadIdx.x];
+      d.rows_part[(uint64_t)threadIdx.x * kRowsPartWaves + blockIdx.x] = t;
+    }
+  };
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
-  if (n0 == 0u || n1 == 0u) return;
-  if (join_expected_nodes(d) > kJoinNodeBudget) {  // the same verdict in every block
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->join_skipped = 1u;
+  if (n0 == 0u || n1 == 0u || join_expected_nodes(d) > kJoinNodeBudget) {
+    // the same verdict in every block: no search; the sweep still runs
+    if (n0 != 0u && n1 != 0u && blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->join_skipped = 1u;
+    if (kSweep) {
+      if (sweeper) sweep();
+      __syncthreads();
+      sweep_store();
+    }
     return;
   }
   const uint32_t* __restrict__ tb = d.hot_t;
-  uint32_t off = 0;
   if (kTbLds) {
-    const uint32_t words = (r << q) >> 5;
-    copy_to_lds(sh, d.hot_t, words);
+    copy_to_lds(sh, d.hot_t, off);
     tb = sh;
-    off = words;  // even: q >= 6
   }
-  u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)(threadIdx.x / kWave) * cap;
-  uint32_t* const lw = sh + off + 2u * cap * (blockDim.x / kWave);
-  uint32_t* const sink = lw + list_words;  // [count, base, next group, -, kCandBuf entries]
   const CandSink cs{sink, sink + 4};
   if (threadIdx.x == 0) sink[0] = sink[2] = 0u;  // visible after the first barrier below
   const uint32_t* g0 = d.hse;
@@ -1222,7 +1331,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   unsigned long long extra = 0;   // nodes counted once per grid
   const uint32_t fw = 4u << (q - 5u);  // words of the four reordered bitmaps
   if (kTbLds && d.delta == 2u && r >= 6u && q >= 10u && q <= 16u && (n1 << 3) >= (1u << q) &&
-      fw + (n0 + 1u) / 2u <= list_words && fw <= 2u * cap * (blockDim.x / kWave)) {
+      fw + (n0 + 1u) / 2u <= list_words && fw <= 2u * cap * jw) {
     const uint32_t rw = 1u << (q - 5u);  // words of one bitmap row
     u32x2* const f1 = reinterpret_cast<u32x2*>(lw);
     uint16_t* const f2 = reinterpret_cast<uint16_t*>(lw + rw);
@@ -1262,10 +1371,12 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
       extra = (unsigned long long)n0 * n1;
     __syncthreads();
     const FoldTables ft{f1, f2, f3, f4, l0, sink + 2};
-    nodes = full ? join_wave_fold<true>(d, cs, tb, ft, stk, cap, n0)
-                 : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
+    nodes = sweeper ? 0u
+            : full  ? join_wave_fold<true>(d, cs, tb, ft, stk, cap, n0)
+                    : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
   } else {
-    auto run = [&](auto lists) {
+    auto run = [&](auto lists) -> uint32_t {
+      if (sweeper) return 0u;
       if (small && full) return join_wave<true, true>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
       if (small) return join_wave<true, false>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
       if (full) return join_wave<false, true>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
@@ -1285,12 +1396,14 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   // One counter update per block (thousands of same-address atomics from every wave would
   // queue behind each other at the end of the kernel): each wave leaves its count in its
   // own stack, which is empty by now.
-  if ((threadIdx.x & 63u) == 0u) stk[0] = u32x2{nodes, 0u};
+  if (sweeper) sweep();  // one call site, where little of the search is live
+  if (!sweeper && (threadIdx.x & 63u) == 0u) stk[0] = u32x2{nodes, 0u};
   __syncthreads();
+  sweep_store();
   const uint32_t nb = sink[0] < kCandBuf ? sink[0] : kCandBuf;  // buffered candidates
   if (threadIdx.x == 0) {
     const u32x2* const stacks = reinterpret_cast<const u32x2*>(sh + off);
-    for (uint32_t w = 0; w < blockDim.x / kWave; ++w) extra += stacks[(uint64_t)w * cap].x;
+    for (uint32_t w = 0; w < jw; ++w) extra += stacks[(uint64_t)w * cap].x;
     atomicAdd(&d.ctrl->join_nodes, extra);
     sink[1] = nb != 0u ? atomicAdd(&d.ctrl->n_cand, nb) : 0u;
   }
@@ -1300,20 +1413,22 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     if (base + j < d.cand_cap) d.cand[base + j] = cs.buf[j];
 }
 
-// Launch shape of the join: one block per compute unit with as many waves (up to 16) as the
-// LDS holds after the hot table (when it is small) and a reserve for the hot lists; the lists
-// take whatever LDS is left.  (Two blocks of 10 waves per CU, with smaller stacks, measured
-// 7 % slower at the config-2 shape than one block of 16.)
-// LDS left free beside the join's block, so that a block of the row-count sweep (which runs
-// on a side stream during the search) fits on the same compute unit.
-constexpr uint32_t kJoinLdsSpare = 1024;
+// Launch shape of the join: one block per compute unit with as many search waves (up to 16,
+// less the sweep waves) as the LDS holds after the hot table (when it is small) and a reserve
+// for the hot lists; the lists take whatever LDS is left.  (Two blocks of 10 waves per CU,
+// with smaller stacks, measured 7 % slower at the config-2 shape than one block of 16.)
+// Sweep waves in each block of the search when the sweep runs inside its launch.  They run at
+// a raised wave priority, so that their loads issue as soon as they can: measured at the
+// config-2 shape, two such waves beside 14 search waves take 125 us per scan, against 131 us
+// with 3 or 4 and 156 us with 1 (137 us with 4 at the default priority).
+constexpr uint32_t kJoinSweepWaves = 2;
 
 struct JoinShape {
   bool tb_lds;
-  uint32_t cap, waves, lds, blocks, list_words;
+  uint32_t cap, waves, sweep_waves, lds, blocks, list_words;
 };
 
-JoinShape join_shape(const Dev& d, int n_cu) {
+JoinShape join_shape(const Dev& d, int n_cu, uint32_t sweep_waves) {
   JoinShape s{};
   s.cap = join_stack_entries(d.delta);
   const uint32_t stack = s.cap * 8u;  // at most 16.5 KiB
@@ -1322,20 +1437,27 @@ JoinShape join_shape(const Dev& d, int n_cu) {
   s.tb_lds = tb <= (32u << 10) && tb + stack + reserve <= kLdsBytes;
   const uint32_t fixed = s.tb_lds ? tb : 0u;
   s.waves = kLdsBytes >= fixed + stack + reserve ? (kLdsBytes - fixed - reserve) / stack : 1u;
-  if (s.waves > kJoinWaves) s.waves = kJoinWaves;
+  if (s.waves > kJoinWaves - sweep_waves) s.waves = kJoinWaves - sweep_waves;
   if (s.waves < 1u) s.waves = 1u;
-  s.lds = kLdsBytes - kJoinLdsSpare;
+  s.sweep_waves = sweep_waves;
+  s.lds = kLdsBytes;
   s.blocks = (uint32_t)n_cu;
-  s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 4u) * 4u) / 4u;
+  s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 4u) * 4u -
+                  sweep_waves * kMaxRP * 4u) / 4u;
   return s;
 }
 
 hipError_t prepare_join() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<true>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_join<false>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+  const void* fns[4] = {reinterpret_cast<const void*>(&k_join<true, false>),
+                        reinterpret_cast<const void*>(&k_join<false, false>),
+                        reinterpret_cast<const void*>(&k_join<true, true>),
+                        reinterpret_cast<const void*>(&k_join<false, true>)};
+  for (const void* f : fns) {
+    hipError_t e =
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Union SLE of host x (Alg. 8): cell z keeps the smallest stamp over the r' rows, i.e. the
@@ -1629,7 +1751,38 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
                                                   double threshold, MlpRef mlp,
                                                   const uint32_t* __restrict__ hosts,
                                                   uint32_t n_hosts,
-                                                  sps_result* __restrict__ direct) {
+                                                  sps_result* __restrict__ direct,
+                                                  uint32_t rows_waves) {
+  __shared__ uint32_t rl[kMaxRP];
+  if (rows_waves) {
+    // the row live counts from the sweep's per-wave partials (each block adds them up; block
+    // 0 also leaves them in the control words)
+    __shared__ uint32_t red[kMaxRP][256 / kWave];
+    uint32_t v[kMaxRP];  // every row's loads issued before any is summed
+#pragma unroll
+    for (int j = 0; j < kMaxRP; ++j) {
+      uint32_t c = 0;
+      if ((uint32_t)j < d.rp)
+        for (uint32_t w = threadIdx.x; w < rows_waves; w += blockDim.x)
+          c += d.rows_part[(uint64_t)j * kRowsPartWaves + w];
+      v[j] = c;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxRP; ++j) {
+      const uint32_t c = wave_sum(v[j]);
+      if (lane_id() == 0 && (uint32_t)j < d.rp) red[j][threadIdx.x / kWave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < d.rp) {
+      uint32_t t = 0;
+      for (uint32_t w = 0; w < blockDim.x / kWave; ++w) t += red[threadIdx.x][w];
+      rl[threadIdx.x] = t;
+      if (blockIdx.x == 0) d.ctrl->row_live[threadIdx.x] = t;
+    }
+  } else if (threadIdx.x < d.rp) {
+    rl[threadIdx.x] = d.ctrl->row_live[threadIdx.x];
+  }
+  __syncthreads();
   const uint32_t n = hosts ? n_hosts : min(d.ctrl->n_cand, d.cand_cap);
   const uint32_t* __restrict__ src = hosts ? hosts : d.cand;
   if (!hosts) {
@@ -1643,7 +1796,7 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
   const uint32_t nfeat = use_mlp ? SPS_MLP_IN : 0u;
   double P = 1.0;  // product of the row setting factors SF(i, k), rows in order
   for (uint32_t i = 0; i < d.rp; ++i)
-    P = P * ((double)d.ctrl->row_live[i] / (double)d.row_len);
+    P = P * ((double)rl[i] / (double)d.row_len);
   const uint32_t c0 = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   // the first host is read before the count is known (in bounds: c0 < the list's capacity)
   const uint32_t x0 = c0 < (hosts ? n_hosts : d.cand_cap) ? src[c0] : 0u;
@@ -1704,65 +1857,73 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
 
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
                        sps_result* out, uint32_t cap, uint32_t* info, const MlpRef& mlp,
-                       bool use_hist, const ScanFork& fork, int n_cu, hipStream_t st) {
+                       bool use_hist, uint32_t mode, int n_cu, hipStream_t st) {
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   ProfScope whole(SPS_STAGE_SCAN, st);
   // The row live counts are needed only by the estimate, and the sweep that makes them
-  // (HBM-bound) shares nothing with the candidate search (ALU-bound, in LDS): with a side
-  // stream the sweep is launched right after the search, beside it, and the estimate waits
-  // for both.  With histograms the counts are a few hundred bins, taken with the SRE pass.
-  const bool side = !use_hist && fork.side != nullptr && (uint32_t)n_cu * 4u <= kRowsPartWaves;
-  if (side) {  // the fork point: everything before the scan has been issued on st
-    hipError_t e = hipEventRecord(fork.ev_fork, st);
-    if (e != hipSuccess) return e;
-  }
+  // (HBM-bound) shares nothing with the candidate search (ALU-bound, in LDS): by default the
+  // sweep runs in the search's own launch, in waves of their own beside the search's, with
+  // no cross-stream synchronization.  With histograms the counts are a few hundred bins,
+  // taken with the SRE pass.  Partial counts: one per block of the search, or one per wave
+  // of k_scan_rows (n_cu blocks of 4 waves).
+  const bool fits = (uint32_t)n_cu * 4u <= kRowsPartWaves;
+  const bool fused = !use_hist && fits && mode != kScanSerial;
+  const bool serial = !use_hist && fits && mode == kScanSerial;
+  uint32_t rows_waves = 0;  // partial counts of the sweep for the estimate to add up
   {
-    // one block per CU: one SRE per lane for the hot SREs (and, without a side stream, the
-    // row live counts first)
-    ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    const uint32_t rows = side ? 0u : (kStatsRows | (use_hist ? kStatsHist : 0u));
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
-                       kStatsSre | rows);
-  }
-  {
-    ProfScope ps(SPS_STAGE_JOIN, st);
-    const JoinShape js = join_shape(d, n_cu);
-    if (js.tb_lds)
-      hipLaunchKernelGGL(k_join<true>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
-                         js.cap, js.list_words);
-    else
-      hipLaunchKernelGGL(k_join<false>, dim3(js.blocks), dim3(js.waves * kWave), js.lds, st, d,
-                         js.cap, js.list_words);
-  }
-  if (side) {
-    // the sweep, issued after the search so that the search's blocks are placed first
-    hipError_t e = hipStreamWaitEvent(fork.side, fork.ev_fork, 0);
-    if (e != hipSuccess) return e;
-    {
-      ProfScope ps(SPS_STAGE_SCAN_ROWS, fork.side);
-      if (d.mode == SPS_MODE_DISCRETE)
-        hipLaunchKernelGGL(k_scan_rows<true>, dim3((uint32_t)n_cu), dim3(256), 0, fork.side, d,
-                           lo, cur);
-      else
-        hipLaunchKernelGGL(k_scan_rows<false>, dim3((uint32_t)n_cu), dim3(256), 0, fork.side, d,
-                           lo, cur);
-      hipLaunchKernelGGL(k_rows_sum, dim3(1), dim3(256), 0, fork.side, d, (uint32_t)n_cu * 4u);
+    // the hot SREs (and, with histograms or when no partials fit, the row live counts)
+    ProfScope ps(SPS_STAGE_SCAN_STATS, st, ProfScope::kKernel);
+    const bool sweep_here = !use_hist && !fits;
+    if (d.q - d.delta >= 6u && !sweep_here) {
+      const uint32_t tiles = d.r << (d.q - d.delta - 6u);
+      const uint32_t blocks = tiles < (uint32_t)n_cu * 8u ? tiles : (uint32_t)n_cu * 8u;
+      launch_k(ps, k_scan_sre, dim3(blocks > d.rp ? blocks : d.rp), dim3(256), 0, st, d, lo,
+               cur, use_hist ? 1u : 0u);
+    } else {
+      const uint32_t rows = use_hist ? (kStatsRows | kStatsHist) : sweep_here ? kStatsRows : 0u;
+      launch_k(ps, k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
+               kStatsSre | rows);
     }
-    // the estimate needs the row live counts
-    e = hipEventRecord(fork.ev_join, fork.side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, fork.ev_join, 0);
-    if (e != hipSuccess) return e;
   }
   {
-    ProfScope ps(SPS_STAGE_ESTIMATE, st);
-    hipLaunchKernelGGL(k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window,
-                       threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr);
+    ProfScope ps(SPS_STAGE_JOIN, st, ProfScope::kKernel);
+    const JoinShape js = join_shape(d, n_cu, fused ? kJoinSweepWaves : 0u);
+    const dim3 grid(js.blocks), block((js.waves + js.sweep_waves) * kWave);
+    if (fused) {
+      rows_waves = js.blocks;  // one partial per block
+      if (js.tb_lds)
+        launch_k(ps, k_join<true, true>, grid, block, js.lds, st, d, js.cap, js.list_words,
+                 js.waves, lo);
+      else
+        launch_k(ps, k_join<false, true>, grid, block, js.lds, st, d, js.cap, js.list_words,
+                 js.waves, lo);
+    } else {
+      if (js.tb_lds)
+        launch_k(ps, k_join<true, false>, grid, block, js.lds, st, d, js.cap, js.list_words,
+                 js.waves, lo);
+      else
+        launch_k(ps, k_join<false, false>, grid, block, js.lds, st, d, js.cap, js.list_words,
+                 js.waves, lo);
+    }
+  }
+  if (serial) {  // the sweep as a kernel of its own after the search
+    ProfScope ps(SPS_STAGE_SCAN_ROWS, st, ProfScope::kKernel);
+    if (d.mode == SPS_MODE_DISCRETE)
+      launch_k(ps, k_scan_rows<true>, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur);
+    else
+      launch_k(ps, k_scan_rows<false>, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur);
+    rows_waves = (uint32_t)n_cu * 4u;
   }
   {
-    ProfScope ps(SPS_STAGE_SORT, st);
+    ProfScope ps(SPS_STAGE_ESTIMATE, st, ProfScope::kKernel);
+    launch_k(ps, k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window, threshold,
+             mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr, rows_waves);
+  }
+  {
+    ProfScope ps(SPS_STAGE_SORT, st, ProfScope::kKernel);
     const uint32_t tiles = (d.cand_cap + kSortTile - 1) / kSortTile;
     const uint32_t blocks = tiles < (uint32_t)n_cu ? tiles : (uint32_t)n_cu;
-    hipLaunchKernelGGL(k_rank_sort, dim3(blocks), dim3(kSortThreads), 0, st, d, out, cap, info);
+    launch_k(ps, k_rank_sort, dim3(blocks), dim3(kSortThreads), 0, st, d, out, cap, info);
   }
   return hipGetLastError();
 }
@@ -1775,16 +1936,16 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
   const uint32_t lo = cur >= window ? cur - window + 1 : 1u;
   {
     // row live counts only (no SREs)
-    ProfScope ps(SPS_STAGE_SCAN_STATS, st);
-    hipLaunchKernelGGL(k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
+    ProfScope ps(SPS_STAGE_SCAN_STATS, st, ProfScope::kKernel);
+    launch_k(ps, k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
                        kStatsRows | (use_hist ? kStatsHist : 0u));
   }
   if (n) {
     uint32_t blocks = (n + 3) / 4;
     if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
-    ProfScope ps(SPS_STAGE_ESTIMATE, st);
-    hipLaunchKernelGGL(k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
-                       hosts, n, out);
+    ProfScope ps(SPS_STAGE_ESTIMATE, st, ProfScope::kKernel);
+    launch_k(ps, k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
+                       hosts, n, out, 0u);
   }
   return launch_scan_reset(d, false, st);  // the counters are clear again
 }
@@ -1808,8 +1969,8 @@ hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const ui
   if (n == 0) return hipSuccess;
   uint64_t blocks = (n + 3) / 4;
   if (blocks > (uint64_t)n_cu * 8) blocks = (uint64_t)n_cu * 8;
-  ProfScope ps(SPS_STAGE_FEATURES, st);
-  hipLaunchKernelGGL(k_features, dim3((uint32_t)blocks), dim3(256), 0, st, d, cur, window,
+  ProfScope ps(SPS_STAGE_FEATURES, st, ProfScope::kKernel);
+  launch_k(ps, k_features, dim3((uint32_t)blocks), dim3(256), 0, st, d, cur, window,
                      hosts, n, x);
   return hipGetLastError();
 }
@@ -1903,8 +2064,8 @@ hipError_t launch_probe_record(const Dev& d, const sps_pkt* pkts, uint64_t n, ui
                                uint32_t* cells, unsigned long long* pos, bool fill,
                                hipStream_t st) {
   if (n == 0) return hipSuccess;
-  ProfScope ps(SPS_STAGE_PROBE, st);
-  hipLaunchKernelGGL(k_probe_record, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, d,
+  ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
+  launch_k(ps, k_probe_record, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, d,
                      reinterpret_cast<const u32x2*>(pkts), n, sle_off, cells, pos,
                      fill ? 1u : 0u);
   return hipGetLastError();
@@ -1914,24 +2075,24 @@ hipError_t launch_probe_replay(uint16_t* state, const uint32_t* cells, const Cla
                                uint16_t value, int blocks, hipStream_t st) {
   uint32_t b = (uint32_t)blocks / kXcds * kXcds;
   if (b < kXcds) b = kXcds;
-  ProfScope ps(SPS_STAGE_PROBE, st);
-  hipLaunchKernelGGL(k_probe_replay, dim3(b), dim3(256), 0, st, state, cells, co, value);
+  ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
+  launch_k(ps, k_probe_replay, dim3(b), dim3(256), 0, st, state, cells, co, value);
   return hipGetLastError();
 }
 
 hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_stores,
                                 uint32_t seed, uint16_t value, int n_cu, hipStream_t st) {
   if (n_stores == 0) return hipSuccess;
-  ProfScope ps(SPS_STAGE_PROBE, st);
-  hipLaunchKernelGGL(k_probe_scatter, dim3(n_cu * 16), dim3(256), 0, st, cells, n_cells,
+  ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
+  launch_k(ps, k_probe_scatter, dim3(n_cu * 16), dim3(256), 0, st, cells, n_cells,
                      n_stores, seed, value);
   return hipGetLastError();
 }
 
 hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, int n_cu,
                                hipStream_t st) {
-  ProfScope ps(SPS_STAGE_PROBE, st);
-  hipLaunchKernelGGL(k_probe_stream, dim3(n_cu), dim3(256), 0, st,
+  ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
+  launch_k(ps, k_probe_stream, dim3(n_cu), dim3(256), 0, st,
                      reinterpret_cast<const u32x4*>(buf), bytes / 16, sum);
   return hipGetLastError();
 }

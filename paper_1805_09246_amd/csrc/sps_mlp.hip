@@ -230,8 +230,8 @@ hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, uint
   const float c1 = (float)(1.0 - pow(b1, (double)step));
   const float c2 = (float)(1.0 - pow(b2, (double)step));
   const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2);
-  ProfScope ps(SPS_STAGE_MLP, st);
-  hipLaunchKernelGGL(k_mlp_adam, dim3((kP + 255) / 256), dim3(256), 0, st, w, m, v, grad, lr,
+  ProfScope ps(SPS_STAGE_MLP, st, ProfScope::kKernel);
+  launch_k(ps, k_mlp_adam, dim3((kP + 255) / 256), dim3(256), 0, st, w, m, v, grad, lr,
                      (float)b1, (float)b2, omb1, omb2, eps, c1, c2);
   return hipGetLastError();
 }
@@ -241,8 +241,8 @@ hipError_t launch_mlp_forward(const float* w, const uint32_t* feat, uint32_t n, 
   if (n == 0) return hipSuccess;
   uint32_t blocks = (n + 3) / 4;
   if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
-  ProfScope ps(SPS_STAGE_MLP, st);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(256), 0, st, w, feat, n, etap, bf16, y);
+  ProfScope ps(SPS_STAGE_MLP, st, ProfScope::kKernel);
+  launch_k(ps, k_mlp_forward, dim3(blocks), dim3(256), 0, st, w, feat, n, etap, bf16, y);
   return hipGetLastError();
 }
 

@@ -52,9 +52,9 @@ def test_c1_full_stream(c1_stream):
     g.close()
 
 
-def test_scan_with_and_without_side_stream(c1_stream):
-    """The row-count sweep on the sketch's side stream (default) and on the scan's own stream
-    give the oracle's scans; the side stream is on by default."""
+def test_scan_sweep_inside_and_after_the_search(c1_stream):
+    """The row-count sweep inside the candidate search's launch (the default) and as a kernel
+    of its own after the search give the oracle's scans."""
     from synth.configs import C1_PARAMS, C1_THRESHOLD, C1_WINDOW
     g, h = sps.Sketch(C1_PARAMS), sps.Sketch(C1_PARAMS)
     assert sps.sps_get_scan_overlap(g.h)
@@ -67,8 +67,8 @@ def test_scan_with_and_without_side_stream(c1_stream):
         h.ingest(dev_pkts(p), s)
         o.ingest(p, s)
         if s >= C1_WINDOW:
-            assert_scan_equal(g, o, C1_WINDOW, C1_THRESHOLD, f"side stream, slice {s}")
-            assert_scan_equal(h, o, C1_WINDOW, C1_THRESHOLD, f"one stream, slice {s}")
+            assert_scan_equal(g, o, C1_WINDOW, C1_THRESHOLD, f"sweep in the search, slice {s}")
+            assert_scan_equal(h, o, C1_WINDOW, C1_THRESHOLD, f"sweep after the search, slice {s}")
     g.close()
     h.close()
 

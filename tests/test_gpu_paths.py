@@ -7,8 +7,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import (assert_scan_equal, assert_state_equal, dev_pkts, gpu_candidates,
-                      import_state)
+from gpu_util import (assert_results_equal, assert_scan_equal, assert_state_equal, dev_pkts,
+                      gpu_candidates, gpu_hot, gpu_row_live, import_state)
 from paper_1805_09246_amd import sps
 
 pytestmark = pytest.mark.gpu
@@ -213,9 +213,54 @@ def test_saturated_sre_array_skips_the_search():
     with pytest.raises(sps.SpsError) as e:
         g.scan(1, 8.0)
     assert e.value.code == sps.SPS_ECAPACITY
+    # the row-count sweep still ran in the skipped search's launch
+    assert np.array_equal(gpu_row_live(g), o.row_live(1)), "row live counts of the skipped scan"
     # a later, unsaturated window of the same sketch is searched as usual
     q = rng.integers(0, 1 << 32, size=(3000, 2), dtype=np.uint64).astype(np.uint32)
     g.ingest(dev_pkts(q), 2)
     o.ingest(q, 2)
     assert_scan_equal(g, o, 1, 8.0, "after saturation")
     g.close()
+
+
+# (q, r, delta): the hot-SRE pass by tiles of 2^(delta+6) SREs (q - delta >= 6; delta 1 leaves
+# waves of the block idle, delta 5 gives each wave 8 groups, q - delta = 6 one tile per row),
+# else one SRE per lane with atomic table bits (q - delta < 6)
+SRE_SHAPES = [(7, 27, 1), (8, 26, 1), (9, 10, 3), (10, 8, 4), (11, 7, 5), (14, 11, 2),
+              (8, 10, 3)]
+
+
+@pytest.mark.parametrize("shape", SRE_SHAPES, ids=lambda s: f"q{s[0]}r{s[1]}d{s[2]}")
+def test_sre_pass_shapes_and_sweep_modes(shape):
+    """Hot bitmap, row live counts, candidates and reports equal the oracle's across the tile
+    shapes of the hot-SRE pass and its one-SRE-per-lane fallback, with the row-count sweep in
+    the search's launch (scan_overlap 1) and after it (2)."""
+    q, r, delta = shape
+    params = dict(q=q, r=r, delta=delta, eta=8, qp=10, rp=3, etap=64, deltap=64, theta=64,
+                  anet_side=0, seed=1000 * q + delta)
+    rng = np.random.default_rng(17 * q + delta)
+    gs = [sps.Sketch(params), sps.Sketch(params)]
+    sps.sps_set_tuning(gs[0].h, scan_overlap=1)
+    sps.sps_set_tuning(gs[1].h, scan_overlap=2)
+    o = oracle.OracleSketch(params)
+    hosts = rng.integers(0, 1 << 32, size=6, dtype=np.uint64).astype(np.uint32)
+    for s in (1, 2):
+        src = rng.integers(0, 1 << 32, size=6 * 150, dtype=np.uint64).astype(np.uint32)
+        planted = np.stack([src, np.repeat(hosts, 150)], 1)
+        noise = rng.integers(0, 1 << 32, size=(1500, 2), dtype=np.uint64).astype(np.uint32)
+        p = np.concatenate([planted, noise])
+        print(f"sre pass q={q} r={r} delta={delta} slice {s}", flush=True)
+        for g in gs:
+            g.ingest(dev_pkts(p), s)
+        o.ingest(p, s)
+        want, ocand = o.scan(2, 64.0)
+        assert np.isin(hosts, want["host"]).all()  # the planted hosts are found
+        for mode, g in zip((1, 2), gs):
+            where = f"q{q} r{r} delta{delta} mode {mode} slice {s}"
+            got = g.scan(2, 64.0, cap=1 << 18)
+            assert np.array_equal(gpu_row_live(g), o.row_live(2)), f"{where}: row live counts"
+            assert np.array_equal(gpu_hot(g), o.hot(2)), f"{where}: hot SREs"
+            assert np.array_equal(gpu_candidates(g), ocand), f"{where}: candidates"
+            assert_results_equal(got, want, where)
+    for g in gs:
+        g.close()
