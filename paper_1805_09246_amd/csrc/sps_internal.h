@@ -14,7 +14,9 @@ constexpr int kMaxR = 32;      // SRE-array rows supported
 constexpr int kMaxBatch = 64;  // routers per batched launch
 constexpr int kMaxMerge = 32;  // sources per merge launch (more are chained)
 constexpr uint32_t kHistBins = 65536;  // one bin per u16 stamp value
-constexpr uint32_t kRowsPartWaves = 4096;  // waves of the side-stream sweep (4 per CU) at most
+// partial row counts of a scan's sweep per row: one per block of the candidate search, or one
+// per wave of k_scan_rows (4 per CU), at most
+constexpr uint32_t kRowsPartWaves = 4096;
 
 // Per-scan counters kept in device memory (one 256-byte block per sketch).  Every scan
 // leaves the working fields zero when it ends (its last kernel clears them), so a scan

@@ -1611,6 +1611,7 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
 // results visible; within this kernel the tiles pass through a release / acquire pair).
 constexpr int kSortThreads = 1024;
 constexpr int kSortTile = 4096;
+constexpr uint32_t kSortMaxBlocks = 16;  // blocks of the sort (tiles taken round robin)
 
 // Bitonic sort of the first P (a power of two, 64 <= P <= kSortTile) keys in LDS.
 __device__ __forceinline__ void lds_bitonic(uint64_t* key, uint32_t P) {
@@ -1921,8 +1922,10 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   }
   {
     ProfScope ps(SPS_STAGE_SORT, st, ProfScope::kKernel);
+    // few blocks: the kept count is known only on the device, and most scans keep fewer than
+    // kSortTile hosts, which block 0 orders alone while the others only start and exit
     const uint32_t tiles = (d.cand_cap + kSortTile - 1) / kSortTile;
-    const uint32_t blocks = tiles < (uint32_t)n_cu ? tiles : (uint32_t)n_cu;
+    const uint32_t blocks = tiles < kSortMaxBlocks ? tiles : kSortMaxBlocks;
     launch_k(ps, k_rank_sort, dim3(blocks), dim3(kSortThreads), 0, st, d, out, cap, info);
   }
   return hipGetLastError();
