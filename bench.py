@@ -623,9 +623,11 @@ def main():
     stage_ms = {k: {"total_ms": round(v[0], 3), "launches": v[1],
                     "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None}
                 for k, v in list(prof_all.items()) + [("scan", prof_scan["scan"])] if v[1]}
-    kernel_names = {"ingest": "k_ingest<false, false>", "scan_stats": "k_scan_sre",
+    compact = (tuning or {}).get("host_classes", 8) > 1
+    kernel_names = {"ingest": "k_ingest_compact" if compact else "k_ingest<false, false>",
+                    "scan_stats": "k_scan_sre",
                     "scan_rows": "k_scan_rows<false>",
-                    "join": "k_join<true, true>" if fused else "k_join<true, false>",
+                    "join": "k_join<true, 1>" if fused else "k_join<true, 0>",
                     "estimate": "k_estimate", "sort": "k_rank_sort", "fill": "k_fill_zero"}
 
     hbm_bytes = {"ingest": rec.n_packets / rec.n_slices * ingest_bytes_per_pkt,

@@ -197,6 +197,47 @@ __global__ void __launch_bounds__(256) k_ingest(Dev d, const u32x2* __restrict__
   }
 }
 
+// The same ingest for the stamp sketch without histograms, with the pairs of the block's
+// class compacted per wave: a wave reads 64 pairs per step and appends those of its class
+// to a queue in LDS (ballot and mbcnt), and hashes and stores only when the queue holds 64
+// of them.  With n_cls classes a pair is the block's one time in n_cls, so without the queue
+// most lanes of every hashing and store instruction would sit idle.
+__global__ void __launch_bounds__(256) k_ingest_compact(Dev d, const u32x2* __restrict__ pkts,
+                                                        uint64_t n, uint16_t stamp,
+                                                        uint32_t n_cls) {
+  __shared__ u32x2 queue[256 / kWave][2 * kWave];
+  const uint32_t lane = lane_id();
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  u32x2* const q = queue[wv];
+  const uint32_t cls = blockIdx.x % n_cls, cls_mask = n_cls - 1u;
+  const uint64_t stride = (uint64_t)(gridDim.x / n_cls) * blockDim.x;
+  uint32_t len = 0;  // pairs in this wave's queue (wave-uniform)
+  for (uint64_t b0 = (uint64_t)(blockIdx.x / n_cls) * blockDim.x + wv * kWave; b0 < n;
+       b0 += stride) {
+    const uint64_t i = b0 + lane;
+    u32x2 pk = {0u, 0u};
+    if (i < n) pk = pkts[i];
+    const uint32_t aip = d.anet_side ? pk.x : pk.y;
+    const bool mine = i < n && (host_class(aip) & cls_mask) == cls;
+    const uint64_t m = __ballot(mine);
+    if (mine)
+      q[len + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = pk;
+    len += (uint32_t)__popcll(m);
+    if (len >= kWave) {  // a full wave of the class's pairs
+      const u32x2 p = q[lane];
+      ingest_pair<false, false>(d, d.sre, d.slea, nullptr, nullptr, p.x, p.y, stamp);
+      len -= kWave;  // the rest (at most 63) moves to the front
+      const u32x2 t = q[kWave + lane];
+      if (lane < len) q[lane] = t;
+    }
+  }
+  if (lane < len) {
+    const u32x2 p = q[lane];
+    ingest_pair<false, false>(d, d.sre, d.slea, nullptr, nullptr, p.x, p.y, stamp);
+  }
+}
+
 // Host classes: 1, 2, 4 or 8 (blocks b and b + n_cls share a class; with 8 a class is one
 // XCD, with fewer a class spans 8 / n_cls XCDs), fewer when the grid is smaller than that.
 uint32_t ingest_classes(int blocks, uint32_t host_classes) {
@@ -218,13 +259,16 @@ hipError_t launch_ingest(const Dev& d, const sps_pkt* pkts, uint64_t n, uint16_t
   const u32x2* p2 = reinterpret_cast<const u32x2*>(pkts);
   if (d.mode == SPS_MODE_DISCRETE)
     launch_k(ps, (k_ingest<false, true>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
-                       n, stamp, n_cls);
+             n, stamp, n_cls);
   else if (track)
     launch_k(ps, (k_ingest<true, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
-                       n, stamp, n_cls);
+             n, stamp, n_cls);
+  else if (n_cls > 1u && threads == 256)
+    launch_k(ps, k_ingest_compact, dim3((uint32_t)b), dim3(threads), 0, st, d, p2, n, stamp,
+             n_cls);
   else
-    launch_k(ps, (k_ingest<false, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2,
-                       n, stamp, n_cls);
+    launch_k(ps, (k_ingest<false, false>), dim3((uint32_t)b), dim3(threads), 0, st, d, p2, n,
+             stamp, n_cls);
   return hipGetLastError();
 }
 
@@ -243,6 +287,9 @@ __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uin
   }
   // tiles go to groups of n_cls consecutive blocks, one host class per block (see k_ingest)
   const uint32_t cls = blockIdx.x % n_cls, cls_mask = n_cls - 1u;
+  __shared__ u32x2 queue[256 / kWave][2 * kWave];
+  const uint32_t lane = lane_id();
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const uint64_t total = t.tile_start[m];
   for (uint64_t w = blockIdx.x / n_cls; w < total; w += gridDim.x / n_cls) {
     uint32_t lo = 0, hi = m;  // find j with tile_start[j] <= w < tile_start[j+1]
@@ -256,6 +303,35 @@ __global__ void __launch_bounds__(256) k_ingest_batched(Dev d, BatchTable t, uin
     if (last > it.n) last = it.n;
     const u32x2* pk2 = reinterpret_cast<const u32x2*>(it.pkts);
     const bool track = kTrack && it.hist != nullptr;  // uniform
+    if (!kTrack && !kBits && n_cls > 1u) {
+      // the class's pairs of this tile compacted per wave, as in k_ingest_compact
+      u32x2* const q = queue[wv];
+      uint32_t len = 0;
+      for (uint64_t b0 = first + wv * kWave; b0 < last; b0 += blockDim.x) {
+        const uint64_t i = b0 + lane;
+        u32x2 pk = {0u, 0u};
+        if (i < last) pk = pk2[i];
+        const uint32_t aip = d.anet_side ? pk.x : pk.y;
+        const bool mine = i < last && (host_class(aip) & cls_mask) == cls;
+        const uint64_t m = __ballot(mine);
+        if (mine)
+          q[len + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = pk;
+        len += (uint32_t)__popcll(m);
+        if (len >= kWave) {
+          const u32x2 p = q[lane];
+          ingest_pair<false, false>(d, it.sre, it.slea, nullptr, nullptr, p.x, p.y, stamp);
+          len -= kWave;
+          const u32x2 t = q[kWave + lane];
+          if (lane < len) q[lane] = t;
+        }
+      }
+      if (lane < len) {
+        const u32x2 p = q[lane];
+        ingest_pair<false, false>(d, it.sre, it.slea, nullptr, nullptr, p.x, p.y, stamp);
+      }
+      continue;
+    }
     for (uint64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
       const u32x2 pk = pk2[i];
       const uint32_t aip = d.anet_side ? pk.x : pk.y;
@@ -288,13 +364,13 @@ hipError_t launch_ingest_batched(const Dev& shape, const BatchTable& t, uint32_t
   ProfScope ps(SPS_STAGE_INGEST_BATCHED, st, ProfScope::kKernel);
   if (shape.mode == SPS_MODE_DISCRETE)
     launch_k(ps, (k_ingest_batched<false, true>), dim3((uint32_t)b), dim3(threads), 0, st,
-                       shape, t, m, tile, stamp, n_cls);
+             shape, t, m, tile, stamp, n_cls);
   else if (track)
     launch_k(ps, (k_ingest_batched<true, false>), dim3((uint32_t)b), dim3(threads), 0, st,
-                       shape, t, m, tile, stamp, n_cls);
+             shape, t, m, tile, stamp, n_cls);
   else
     launch_k(ps, (k_ingest_batched<false, false>), dim3((uint32_t)b), dim3(threads), 0, st,
-                       shape, t, m, tile, stamp, n_cls);
+             shape, t, m, tile, stamp, n_cls);
   return hipGetLastError();
 }
 
@@ -315,7 +391,7 @@ hipError_t launch_fill_zero(void* p, uint64_t bytes, hipStream_t st) {
   if (blocks > 8192) blocks = 8192;
   ProfScope ps(SPS_STAGE_FILL, st, ProfScope::kKernel);
   launch_k(ps, k_fill_zero, dim3((uint32_t)blocks), dim3(256), 0, st,
-                     reinterpret_cast<u32x4*>(p), nvec);
+           reinterpret_cast<u32x4*>(p), nvec);
   return hipGetLastError();
 }
 
@@ -354,7 +430,7 @@ hipError_t launch_merge(uint16_t* dst, const uint16_t* const* srcs, uint32_t nsr
     for (uint32_t j = 0; j < k; ++j) s.p[j] = reinterpret_cast<const u16x8*>(srcs[b + j]);
     ProfScope ps(SPS_STAGE_MERGE, st, ProfScope::kKernel);
     launch_k(ps, k_merge_max, dim3((uint32_t)blocks), dim3(256), 0, st,
-                       reinterpret_cast<u16x8*>(dst), s, k, nvec, bits ? 1 : 0);
+             reinterpret_cast<u16x8*>(dst), s, k, nvec, bits ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -380,7 +456,7 @@ hipError_t launch_rebase(uint16_t* p, uint64_t bytes, uint32_t offset, hipStream
   if (blocks > 8192) blocks = 8192;
   ProfScope ps(SPS_STAGE_REBASE, st, ProfScope::kKernel);
   launch_k(ps, k_rebase, dim3((uint32_t)blocks), dim3(256), 0, st,
-                     reinterpret_cast<u16x8*>(p), nvec, offset);
+           reinterpret_cast<u16x8*>(p), nvec, offset);
   return hipGetLastError();
 }
 
@@ -1264,14 +1340,17 @@ constexpr double kJoinNodeBudget = 68719476736.0;
 // live counts meanwhile (one lane of the sweep each, partial counts per wave), so the
 // HBM-bound sweep runs beside the ALU-bound search in the same launch.  Sweep waves take part
 // in the block's barriers and leave the stacks, lists and candidate buffer alone.
-template <bool kTbLds, bool kSweep>
+// kSweep: 0 no sweep; 1 the stamp array; 2 the discrete variant's bit array (a symbol of its
+// own, so that profiles keep the two apart).
+constexpr int kSweepNone = 0, kSweepStamps = 1, kSweepBits = 2;
+template <bool kTbLds, int kSweep>
 __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
                                                           uint32_t list_words, uint32_t jw,
                                                           uint32_t lo) {
   extern __shared__ uint32_t sh[];
   const uint32_t q = d.q, r = d.r;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const bool sweeper = kSweep && wave >= jw;
+  const bool sweeper = kSweep != kSweepNone && wave >= jw;
   const uint32_t off = kTbLds ? (r << q) >> 5 : 0u;  // words of the table in LDS (even)
   // stacks for the search waves only (a sweep wave's pointer is never used)
   u32x2* const stk = reinterpret_cast<u32x2*>(sh + off) + (uint64_t)wave * cap;
@@ -1296,7 +1375,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   };
   // after a barrier: the block's counts, one partial per block and row
   auto sweep_store = [&]() {
-    if (kSweep && threadIdx.x < d.rp) {
+    if (kSweep != kSweepNone && threadIdx.x < d.rp) {
       uint32_t t = 0;
       for (uint32_t w = 0; w < blockDim.x / kWave - jw; ++w) t += swc[w * kMaxRP + threadIdx.x];
       d.rows_part[(uint64_t)threadIdx.x * kRowsPartWaves + blockIdx.x] = t;
@@ -1306,7 +1385,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   if (n0 == 0u || n1 == 0u || join_expected_nodes(d) > kJoinNodeBudget) {
     // the same verdict in every block: no search; the sweep still runs
     if (n0 != 0u && n1 != 0u && blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->join_skipped = 1u;
-    if (kSweep) {
+    if (kSweep != kSweepNone) {
       if (sweeper) sweep();
       __syncthreads();
       sweep_store();
@@ -1448,10 +1527,12 @@ JoinShape join_shape(const Dev& d, int n_cu, uint32_t sweep_waves) {
 }
 
 hipError_t prepare_join() {
-  const void* fns[4] = {reinterpret_cast<const void*>(&k_join<true, false>),
-                        reinterpret_cast<const void*>(&k_join<false, false>),
-                        reinterpret_cast<const void*>(&k_join<true, true>),
-                        reinterpret_cast<const void*>(&k_join<false, true>)};
+  const void* fns[6] = {reinterpret_cast<const void*>(&k_join<true, kSweepNone>),
+                        reinterpret_cast<const void*>(&k_join<false, kSweepNone>),
+                        reinterpret_cast<const void*>(&k_join<true, kSweepStamps>),
+                        reinterpret_cast<const void*>(&k_join<false, kSweepStamps>),
+                        reinterpret_cast<const void*>(&k_join<true, kSweepBits>),
+                        reinterpret_cast<const void*>(&k_join<false, kSweepBits>)};
   for (const void* f : fns) {
     hipError_t e =
         hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
@@ -1890,21 +1971,29 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
     ProfScope ps(SPS_STAGE_JOIN, st, ProfScope::kKernel);
     const JoinShape js = join_shape(d, n_cu, fused ? kJoinSweepWaves : 0u);
     const dim3 grid(js.blocks), block((js.waves + js.sweep_waves) * kWave);
-    if (fused) {
-      rows_waves = js.blocks;  // one partial per block
+    if (fused) rows_waves = js.blocks;  // one partial per block
+    const bool bits = d.mode == SPS_MODE_DISCRETE;
+    if (fused && bits) {
       if (js.tb_lds)
-        launch_k(ps, k_join<true, true>, grid, block, js.lds, st, d, js.cap, js.list_words,
-                 js.waves, lo);
+        launch_k(ps, k_join<true, kSweepBits>, grid, block, js.lds, st, d, js.cap,
+                 js.list_words, js.waves, lo);
       else
-        launch_k(ps, k_join<false, true>, grid, block, js.lds, st, d, js.cap, js.list_words,
-                 js.waves, lo);
+        launch_k(ps, k_join<false, kSweepBits>, grid, block, js.lds, st, d, js.cap,
+                 js.list_words, js.waves, lo);
+    } else if (fused) {
+      if (js.tb_lds)
+        launch_k(ps, k_join<true, kSweepStamps>, grid, block, js.lds, st, d, js.cap,
+                 js.list_words, js.waves, lo);
+      else
+        launch_k(ps, k_join<false, kSweepStamps>, grid, block, js.lds, st, d, js.cap,
+                 js.list_words, js.waves, lo);
     } else {
       if (js.tb_lds)
-        launch_k(ps, k_join<true, false>, grid, block, js.lds, st, d, js.cap, js.list_words,
-                 js.waves, lo);
+        launch_k(ps, k_join<true, kSweepNone>, grid, block, js.lds, st, d, js.cap,
+                 js.list_words, js.waves, lo);
       else
-        launch_k(ps, k_join<false, false>, grid, block, js.lds, st, d, js.cap, js.list_words,
-                 js.waves, lo);
+        launch_k(ps, k_join<false, kSweepNone>, grid, block, js.lds, st, d, js.cap,
+                 js.list_words, js.waves, lo);
     }
   }
   if (serial) {  // the sweep as a kernel of its own after the search
@@ -1941,14 +2030,14 @@ hipError_t launch_estimate_hosts(const Dev& d, uint32_t cur, uint32_t window,
     // row live counts only (no SREs)
     ProfScope ps(SPS_STAGE_SCAN_STATS, st, ProfScope::kKernel);
     launch_k(ps, k_scan_stats, dim3((uint32_t)n_cu), dim3(256), 0, st, d, lo, cur,
-                       kStatsRows | (use_hist ? kStatsHist : 0u));
+             kStatsRows | (use_hist ? kStatsHist : 0u));
   }
   if (n) {
     uint32_t blocks = (n + 3) / 4;
     if (blocks > (uint32_t)n_cu * 8) blocks = (uint32_t)n_cu * 8;
     ProfScope ps(SPS_STAGE_ESTIMATE, st, ProfScope::kKernel);
     launch_k(ps, k_estimate, dim3(blocks), dim3(256), 0, st, d, cur, lo, window, 0.0, mlp,
-                       hosts, n, out, 0u);
+             hosts, n, out, 0u);
   }
   return launch_scan_reset(d, false, st);  // the counters are clear again
 }
@@ -1974,7 +2063,7 @@ hipError_t launch_features(const Dev& d, uint32_t cur, uint32_t window, const ui
   if (blocks > (uint64_t)n_cu * 8) blocks = (uint64_t)n_cu * 8;
   ProfScope ps(SPS_STAGE_FEATURES, st, ProfScope::kKernel);
   launch_k(ps, k_features, dim3((uint32_t)blocks), dim3(256), 0, st, d, cur, window,
-                     hosts, n, x);
+           hosts, n, x);
   return hipGetLastError();
 }
 
@@ -2069,8 +2158,8 @@ hipError_t launch_probe_record(const Dev& d, const sps_pkt* pkts, uint64_t n, ui
   if (n == 0) return hipSuccess;
   ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
   launch_k(ps, k_probe_record, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, d,
-                     reinterpret_cast<const u32x2*>(pkts), n, sle_off, cells, pos,
-                     fill ? 1u : 0u);
+           reinterpret_cast<const u32x2*>(pkts), n, sle_off, cells, pos,
+           fill ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -2088,7 +2177,7 @@ hipError_t launch_probe_scatter(uint16_t* cells, uint64_t n_cells, uint64_t n_st
   if (n_stores == 0) return hipSuccess;
   ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
   launch_k(ps, k_probe_scatter, dim3(n_cu * 16), dim3(256), 0, st, cells, n_cells,
-                     n_stores, seed, value);
+           n_stores, seed, value);
   return hipGetLastError();
 }
 
@@ -2096,7 +2185,7 @@ hipError_t launch_probe_stream(const void* buf, uint64_t bytes, uint32_t* sum, i
                                hipStream_t st) {
   ProfScope ps(SPS_STAGE_PROBE, st, ProfScope::kKernel);
   launch_k(ps, k_probe_stream, dim3(n_cu), dim3(256), 0, st,
-                     reinterpret_cast<const u32x4*>(buf), bytes / 16, sum);
+           reinterpret_cast<const u32x4*>(buf), bytes / 16, sum);
   return hipGetLastError();
 }
 

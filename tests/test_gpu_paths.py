@@ -48,6 +48,20 @@ def test_report_order_paths(n_hosts):
     g.close()
 
 
+@pytest.mark.parametrize("cand_cap", [1100, 1107])
+def test_report_at_candidate_capacity(cand_cap):
+    """1100 candidates, all kept: a candidate list and kept list exactly as long as the
+    capacity (and one 7 entries longer) give the oracle's full report without overflow."""
+    p = _hosts_with_peers(1100, 12, 1100)
+    params = dict(ORDER, cand_cap=cand_cap)
+    g, o = sps.Sketch(params), oracle.OracleSketch(params)
+    g.ingest(dev_pkts(p), 1)
+    o.ingest(p, 1)
+    got = assert_scan_equal(g, o, 1, 4.0, f"cand_cap {cand_cap}")
+    assert len(got) == 1100
+    g.close()
+
+
 def _crafted(params, hot_cols, cur=3, seed=0):
     """SRE state whose hot SREs are exactly hot_cols[i] in row i (three cells stamped `cur`,
     the hot cut for eta = 8), SLE array empty; the same state in a GPU and an oracle sketch."""
