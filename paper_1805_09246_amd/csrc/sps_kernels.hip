@@ -1296,22 +1296,40 @@ __device__ __forceinline__ uint32_t join_wave_fold(const Dev& d, const CandSink&
 
 // Block-wide copy from global memory into LDS with eight loads per thread in flight before
 // the first store (a plain strided loop waits out each load's latency in turn).
+// n elements copied by the block's first nt threads (nt = blockDim.x: the whole block)
 template <typename D, typename S>
 __device__ __forceinline__ void copy_to_lds(D* __restrict__ dst, const S* __restrict__ src,
-                                            uint32_t n) {
-  for (uint32_t base = 0; base < n; base += 8u * blockDim.x) {
+                                            uint32_t n, uint32_t nt) {
+  for (uint32_t base = 0; base < n; base += 8u * nt) {
     S v[8];
 #pragma unroll
     for (uint32_t u = 0; u < 8u; ++u) {
-      const uint32_t i = base + u * blockDim.x + threadIdx.x;
+      const uint32_t i = base + u * nt + threadIdx.x;
       v[u] = i < n ? src[i] : S(0);
     }
 #pragma unroll
     for (uint32_t u = 0; u < 8u; ++u) {
-      const uint32_t i = base + u * blockDim.x + threadIdx.x;
+      const uint32_t i = base + u * nt + threadIdx.x;
       if (i < n) dst[i] = (D)v[u];
     }
   }
+}
+template <typename D, typename S>
+__device__ __forceinline__ void copy_to_lds(D* __restrict__ dst, const S* __restrict__ src,
+                                            uint32_t n) {
+  copy_to_lds(dst, src, n, blockDim.x);
+}
+
+// Barrier of the search waves alone, for a launch whose other waves sweep meanwhile and must
+// not wait: each wave adds one to an LDS counter (zeroed before the waves split) and waits,
+// sleeping, until all `jw` search waves have arrived for this generation.
+__device__ __forceinline__ void search_sync(uint32_t* ctr, uint32_t jw, uint32_t& gen) {
+  ++gen;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (lane_id() == 0u) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < jw * gen)
+    __builtin_amdgcn_s_sleep(1);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words]
@@ -1358,6 +1376,17 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   // [count, base, next group, -, kCandBuf entries, sweep counts (kMaxRP per sweep wave)]
   uint32_t* const sink = lw + list_words;
   uint32_t* const swc = sink + 4u + kCandBuf;
+  uint32_t* const sctr = swc + (blockDim.x / kWave - jw) * kMaxRP;  // search_sync's counter
+  // threads of the search: with sweep waves the search's loops and barriers leave them out, so
+  // they start sweeping at once
+  const uint32_t nt = kSweep != kSweepNone ? jw * kWave : blockDim.x;
+  uint32_t gen = 0;
+  auto sync = [&]() {
+    if constexpr (kSweep != kSweepNone)
+      search_sync(sctr, jw, gen);
+    else
+      __syncthreads();
+  };
   // a sweep wave's share of the sweep: its per-row counts into the LDS
   auto sweep = [&]() {
     __builtin_amdgcn_s_setprio(2);  // ahead of the search's waves for issue
@@ -1381,6 +1410,10 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
       d.rows_part[(uint64_t)threadIdx.x * kRowsPartWaves + blockIdx.x] = t;
     }
   };
+  if (kSweep != kSweepNone) {
+    if (threadIdx.x == 0) *sctr = 0u;
+    __syncthreads();  // the counter is zero before the waves split
+  }
   const uint32_t n0 = d.ctrl->hse_count[0], n1 = d.ctrl->hse_count[1];
   if (n0 == 0u || n1 == 0u || join_expected_nodes(d) > kJoinNodeBudget) {
     // the same verdict in every block: no search; the sweep still runs
@@ -1392,12 +1425,17 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     }
     return;
   }
+  const CandSink cs{sink, sink + 4};
+  uint32_t nodes = 0;             // nodes this wave expanded
+  unsigned long long extra = 0;   // nodes counted once per grid
+  if (sweeper) {
+    sweep();
+  } else {
   const uint32_t* __restrict__ tb = d.hot_t;
   if (kTbLds) {
-    copy_to_lds(sh, d.hot_t, off);
+    copy_to_lds(sh, d.hot_t, off, nt);
     tb = sh;
   }
-  const CandSink cs{sink, sink + 4};
   if (threadIdx.x == 0) sink[0] = sink[2] = 0u;  // visible after the first barrier below
   const uint32_t* g0 = d.hse;
   const uint32_t* g1 = d.hse + (1u << q);
@@ -1406,8 +1444,6 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   const bool full = (r - 2u) * d.delta + q <= 32u;
   // rows 1-3 in bulk: delta = 2, rows at least 1/8 hot (row 1 stands for all), the tables
   // (3 bitmaps of 2^q bits and the row-0 list) fit in the LDS left after the stacks
-  uint32_t nodes;                 // nodes this wave expanded
-  unsigned long long extra = 0;   // nodes counted once per grid
   const uint32_t fw = 4u << (q - 5u);  // words of the four reordered bitmaps
   if (kTbLds && d.delta == 2u && r >= 6u && q >= 10u && q <= 16u && (n1 << 3) >= (1u << q) &&
       fw + (n0 + 1u) / 2u <= list_words && fw <= 2u * cap * jw) {
@@ -1419,13 +1455,13 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     uint16_t* const l0 = reinterpret_cast<uint16_t*>(lw + fw);
     // rows 1-4 of the plain bitmap, staged where the stacks will be
     uint32_t* const h = reinterpret_cast<uint32_t*>(sh + off);
-    copy_to_lds(h, d.hot + rw, fw);
-    copy_to_lds(l0, g0, n0);
-    __syncthreads();
+    copy_to_lds(h, d.hot + rw, fw, nt);
+    copy_to_lds(l0, g0, n0, nt);
+    sync();
     auto hot_bit = [&](uint32_t row, uint32_t col) {  // row >= 1
       return (h[(row - 1u) * rw + (col >> 5)] >> (col & 31u)) & 1u;
     };
-    for (uint32_t c = threadIdx.x; c < (1u << (q - 6u)); c += blockDim.x) {
+    for (uint32_t c = threadIdx.x; c < (1u << (q - 6u)); c += nt) {
       u32x2 o = {0u, 0u};
       for (uint32_t j = 0; j < 64u; ++j) {
         const uint32_t bit = hot_bit(1u, 64u * c + j), p = fold_pos(j);
@@ -1434,7 +1470,7 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
       f1[c] = o;
     }
     const uint32_t wn = 1u << (q - 4u);
-    for (uint32_t c = threadIdx.x; c < wn; c += blockDim.x) {
+    for (uint32_t c = threadIdx.x; c < wn; c += nt) {
       uint32_t o2 = 0, o3 = 0, o4 = 0;
       for (uint32_t j = 0; j < 16u; ++j) {
         const uint32_t t = j >> 2, b = j & 3u;  // slot t, bit b
@@ -1448,14 +1484,12 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     }
     if (blockIdx.x == 0)  // row-1 tuples: every pair (he0, he1)
       extra = (unsigned long long)n0 * n1;
-    __syncthreads();
+    sync();
     const FoldTables ft{f1, f2, f3, f4, l0, sink + 2};
-    nodes = sweeper ? 0u
-            : full  ? join_wave_fold<true>(d, cs, tb, ft, stk, cap, n0)
-                    : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
+    nodes = full ? join_wave_fold<true>(d, cs, tb, ft, stk, cap, n0)
+                 : join_wave_fold<false>(d, cs, tb, ft, stk, cap, n0);
   } else {
     auto run = [&](auto lists) -> uint32_t {
-      if (sweeper) return 0u;
       if (small && full) return join_wave<true, true>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
       if (small) return join_wave<true, false>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
       if (full) return join_wave<false, true>(d, cs, tb, stk, cap, lists, n0, n1, sink + 2);
@@ -1463,19 +1497,19 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
     };
     if (q <= 16u && (n0 + n1 + 1u) / 2u <= list_words) {  // u16 lists in LDS
       uint16_t* const h = reinterpret_cast<uint16_t*>(lw);
-      copy_to_lds(h, g0, n0);
-      copy_to_lds(h + n0, g1, n1);
-      __syncthreads();
+      copy_to_lds(h, g0, n0, nt);
+      copy_to_lds(h + n0, g1, n1, nt);
+      sync();
       nodes = run(HotLists<uint16_t>{h, h + n0});
     } else {
-      __syncthreads();
+      sync();
       nodes = run(HotLists<uint32_t>{g0, g1});
     }
   }
+  }  // the search
   // One counter update per block (thousands of same-address atomics from every wave would
   // queue behind each other at the end of the kernel): each wave leaves its count in its
   // own stack, which is empty by now.
-  if (sweeper) sweep();  // one call site, where little of the search is live
   if (!sweeper && (threadIdx.x & 63u) == 0u) stk[0] = u32x2{nodes, 0u};
   __syncthreads();
   sweep_store();
@@ -1522,7 +1556,7 @@ JoinShape join_shape(const Dev& d, int n_cu, uint32_t sweep_waves) {
   s.lds = kLdsBytes;
   s.blocks = (uint32_t)n_cu;
   s.list_words = (s.lds - fixed - s.waves * stack - (kCandBuf + 4u) * 4u -
-                  sweep_waves * kMaxRP * 4u) / 4u;
+                  (sweep_waves ? (sweep_waves * kMaxRP + 1u) * 4u : 0u)) / 4u;
   return s;
 }
 
