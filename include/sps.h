@@ -53,8 +53,10 @@ extern "C" {
 #define SPS_INFO_KEPT 0      /* hosts kept by the final filter */
 #define SPS_INFO_CAND 1      /* candidates recovered from the SRE array (may exceed capacity) */
 #define SPS_INFO_FLAGS 2     /* bit 0: candidate buffer overflow; bit 1: result buffer overflow;
-                                bit 2 (with bit 0): candidate search not run -- its expected size
-                                from the rows' hot rates passed 2^36 nodes (SRE array saturated) */
+                                bit 2 (with bit 0): candidate search not run or not completed --
+                                its expected size from the rows' hot rates passed 2^36 nodes (SRE
+                                array saturated), or its waves timed out waiting for each other
+                                (about a second; not expected) */
 #define SPS_INFO_HSE0 3      /* hot SREs in row 0 */
 #define SPS_INFO_HSE1 4      /* hot SREs in row 1 */
 #define SPS_INFO_NODES_LO 5  /* candidate-search nodes expanded (low 32 bits; Alg. 4-5 tuples */

@@ -1322,14 +1322,27 @@ __device__ __forceinline__ void copy_to_lds(D* __restrict__ dst, const S* __rest
 
 // Barrier of the search waves alone, for a launch whose other waves sweep meanwhile and must
 // not wait: each wave adds one to an LDS counter (zeroed before the waves split) and waits,
-// sleeping, until all `jw` search waves have arrived for this generation.
-__device__ __forceinline__ void search_sync(uint32_t* ctr, uint32_t jw, uint32_t& gen) {
+// sleeping, until all `jw` search waves have arrived for this generation.  Every search wave
+// calls it the same number of times (the prologue's branches are block-uniform); the wait is
+// still bounded (about 2^26 sleeps, over a second): past it the wave goes on and the result
+// is false, which the caller reports as a failed search instead of hanging.
+__device__ __forceinline__ bool search_sync(uint32_t* ctr, uint32_t jw, uint32_t& gen) {
   ++gen;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  if (lane_id() == 0u) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < jw * gen)
+  if (lane_id() == 0u)
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  bool ok = true;
+  for (uint32_t spins = 0;
+       __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < jw * gen;
+       ++spins) {
+    if (spins == (1u << 26)) {
+      ok = false;
+      break;
+    }
     __builtin_amdgcn_s_sleep(1);
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return ok;
 }
 
 // LDS: [hot table (kTbLds)] [stacks: waves x cap entries] [hot lists, list_words words]
@@ -1382,10 +1395,11 @@ __global__ void __launch_bounds__(kJoinWaves * 64) k_join(Dev d, uint32_t cap,
   const uint32_t nt = kSweep != kSweepNone ? jw * kWave : blockDim.x;
   uint32_t gen = 0;
   auto sync = [&]() {
-    if constexpr (kSweep != kSweepNone)
-      search_sync(sctr, jw, gen);
-    else
+    if constexpr (kSweep != kSweepNone) {
+      if (!search_sync(sctr, jw, gen) && lane_id() == 0u) d.ctrl->join_skipped = 1u;
+    } else {
       __syncthreads();
+    }
   };
   // a sweep wave's share of the sweep: its per-row counts into the LDS
   auto sweep = [&]() {
