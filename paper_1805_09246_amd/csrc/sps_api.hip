@@ -108,7 +108,8 @@ uint64_t splitmix64_next(uint64_t& st) {
 }
 
 struct Layout {
-  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, sorted, skeys, part, hist, total;
+  uint64_t ctrl, info, sre, slea, hot, hot_t, hse, cand, kept, wkept, sorted, skeys, part,
+      hist, total;
   uint64_t row_len, row_stride, sre_bytes, slea_bytes;
 };
 
@@ -136,7 +137,9 @@ Layout layout_of(const sps_params* p) {
   L.hot_t = o;  o += round_up(((uint64_t)p->r << p->q) / 8, 256);
   L.hse = o;    o += round_up(((uint64_t)2 << p->q) * 4, 256);
   L.cand = o;   o += round_up(cap * 4, 256);
-  L.kept = o;   o += round_up(cap * sizeof(sps_result), 256);
+  L.kept = o;   o += round_up((uint64_t)sps::kEstWaves * sps::kept_region((uint32_t)cap) *
+                                sizeof(sps_result), 256);
+  L.wkept = o;  o += sps::kEstWaves * 4;
   L.sorted = o; o += round_up(cap * sizeof(sps_result), 256);
   L.skeys = o;  o += round_up(cap * 8, 256);
   L.part = o;   o += (uint64_t)sps::kMaxRP * sps::kRowsPartWaves * 4;
@@ -460,6 +463,7 @@ int sps_create(const sps_params* p, void* d_mem, size_t bytes, sps_sketch** out)
   d.hse = reinterpret_cast<uint32_t*>(b + L.hse);
   d.cand = reinterpret_cast<uint32_t*>(b + L.cand);
   d.kept = reinterpret_cast<sps_result*>(b + L.kept);
+  d.wave_kept = reinterpret_cast<uint32_t*>(b + L.wkept);
   d.skeys = reinterpret_cast<uint64_t*>(b + L.skeys);
   d.rows_part = reinterpret_cast<uint32_t*>(b + L.part);
   d.hist = p->row_counts ? reinterpret_cast<uint32_t*>(b + L.hist) : nullptr;

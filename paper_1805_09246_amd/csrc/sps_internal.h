@@ -17,6 +17,13 @@ constexpr uint32_t kHistBins = 65536;  // one bin per u16 stamp value
 // partial row counts of a scan's sweep per row: one per block of the candidate search, or one
 // per wave of k_scan_rows (4 per CU), at most
 constexpr uint32_t kRowsPartWaves = 4096;
+// waves of a scan's estimate launch; wave w handles candidates w, w + kEstWaves, ... and
+// keeps its hosts in a region of its own of the kept list
+constexpr uint32_t kEstWaves = 2048;
+// entries of one estimate wave's region of the kept list: room for every candidate it can get
+inline __host__ __device__ uint32_t kept_region(uint32_t cand_cap) {
+  return (cand_cap + kEstWaves - 1) / kEstWaves;
+}
 
 // Per-scan counters kept in device memory (one 256-byte block per sketch).  Every scan
 // leaves the working fields zero when it ends (its last kernel clears them), so a scan
@@ -25,7 +32,7 @@ struct Ctrl {
   uint32_t row_live[kMaxRP];  // live cells of every SLE-array row (Def. 4 numerators)
   uint32_t hse_count[2];      // hot SREs found in rows 0 and 1
   uint32_t n_cand;            // candidates recovered (counts past the capacity)
-  uint32_t n_kept;            // hosts kept by the final filter (counts past the capacity)
+  uint32_t n_kept;            // hosts kept by the final filter (set by the ordering kernel)
   unsigned long long join_nodes;  // nodes the candidate search expanded
   uint32_t sort_done;     // blocks of the ordering kernel done with their tiles
   uint32_t pad0;
@@ -59,7 +66,9 @@ struct Dev {
                           // (low << delta) + top of row i is hot_i[low | top << (q - delta)]
   uint32_t* hse;          // [2][2^q] hot-SRE column lists of rows 0 and 1
   uint32_t* cand;         // [cand_cap] recovered candidates
-  sps_result* kept;       // [cand_cap] kept hosts, unordered
+  sps_result* kept;       // [kEstWaves][kept_region(cand_cap)] kept hosts: estimate wave w
+                          // leaves its wave_kept[w] hosts at the start of region w
+  uint32_t* wave_kept;    // [kEstWaves] hosts each estimate wave kept in the last scan
   uint64_t* skeys;        // [cand_cap] (host << 32 | index into kept), sorted per 4096-tile
   Ctrl* ctrl;
   uint32_t* rows_part;    // [kMaxRP][kRowsPartWaves] partial row live counts of a scan's

@@ -1727,7 +1727,8 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
 }
 
 // Stage 4: order the kept hosts ascending (hosts are distinct; keys are host << 32 | index
-// into the unordered kept list, padded with keys above every host).
+// into the kept list, padded with keys above every host).  Every block first turns the
+// estimate waves' kept counts into the ordinal of each wave's first host (a prefix sum).
 //   n <= 1024: block 0 alone, one key per thread, a bitonic network in registers with
 //              cross-lane moves for partners closer than 64 and LDS beyond.
 //   n <= 4096: block 0 alone, a bitonic sort of the whole list in LDS.
@@ -1794,19 +1795,71 @@ __device__ void scan_finish(const Dev& d, uint32_t cap, uint32_t* __restrict__ i
   for (uint32_t i = threadIdx.x; i < kCtrlWorkingWords; i += blockDim.x) w[i] = 0;
 }
 
+// Offsets of the kept hosts.  Estimate wave w left wave_kept[w] hosts at the start of region
+// w of the kept list; pre[w] receives the number of kept hosts in the waves before w (the
+// ordinal of its first one).  Two waves' counts per thread (a, b); returns the total.
+__device__ __forceinline__ uint32_t kept_offsets(const Dev& d, uint32_t* pre, uint32_t& a,
+                                                 uint32_t& b) {
+  static_assert(kEstWaves == 2u * kSortThreads, "two estimate waves per thread of the sort");
+  __shared__ uint32_t wave_tot[kSortThreads / kWave];
+  const uint32_t t = threadIdx.x;
+  const uint32_t region = kept_region(d.cand_cap);  // no wave keeps more
+  a = min(d.wave_kept[2 * t], region);
+  b = min(d.wave_kept[2 * t + 1], region);
+  const uint32_t inc = wave_incl_scan(a + b);
+  if (lane_id() == kWave - 1) wave_tot[t / kWave] = inc;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (uint32_t w = 0; w < kSortThreads / kWave; ++w) {
+    const uint32_t v = wave_tot[w];
+    before += w < t / kWave ? v : 0u;
+    total += v;
+  }
+  pre[2 * t] = before + inc - a - b;
+  pre[2 * t + 1] = before + inc - b;
+  __syncthreads();
+  return min(total, d.cand_cap);  // at most one kept host per candidate
+}
+
+// Index into the kept list of kept host number i (i < total): it belongs to the last wave
+// whose offset is at most i.
+__device__ __forceinline__ uint32_t kept_slot(const uint32_t* pre, uint32_t region, uint32_t i) {
+  uint32_t lo = 0, hi = kEstWaves;  // pre[lo] <= i, and i < the offset past wave hi - 1
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo * region + (i - pre[lo]);
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
                                                             uint32_t cap,
                                                             uint32_t* __restrict__ info) {
   __shared__ uint64_t key[kSortTile];
+  __shared__ uint32_t pre[kEstWaves];
   __shared__ uint32_t last;
   Ctrl* c = d.ctrl;
-  const uint32_t n = min(c->n_kept, d.cand_cap);
+  uint32_t cnt_a, cnt_b;
+  // the same in every lane; said so, the loops below stay scalar
+  const uint32_t n = __builtin_amdgcn_readfirstlane(kept_offsets(d, pre, cnt_a, cnt_b));
+  const uint32_t region = kept_region(d.cand_cap);
   const bool tiled = out && n > (uint32_t)kSortTile;
   if (!tiled && blockIdx.x != 0) return;  // block 0 orders short lists alone
+  if (out && !tiled) {
+    // key[i] = host << 32 | index into the kept list, for kept host number i
+    for (uint32_t h = 0; h < 2u; ++h) {
+      const uint32_t w = 2 * threadIdx.x + h, cnt = h ? cnt_b : cnt_a;
+      for (uint32_t l = 0; l < cnt && pre[w] + l < n; ++l) {
+        const uint32_t slot = w * region + l;
+        key[pre[w] + l] = ((uint64_t)d.kept[slot].host << 32) | slot;
+      }
+    }
+    __syncthreads();
+  }
   if (out && n <= (uint32_t)kSortThreads) {
     const uint32_t P = pow2_at_least(n, 64u);
     const uint32_t i = threadIdx.x;
-    uint64_t v = i < n ? ((uint64_t)d.kept[i].host << 32) | i : ~0ull;
+    uint64_t v = i < n ? key[i] : ~0ull;
     for (uint32_t k = 2; k <= P; k <<= 1) {
       for (uint32_t j = k >> 1; j > 0; j >>= 1) {
         uint64_t w;
@@ -1828,8 +1881,7 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
     if (i < m) out[i] = d.kept[(uint32_t)v];
   } else if (out && !tiled) {
     const uint32_t P = pow2_at_least(n, 64u);
-    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x)
-      key[i] = i < n ? ((uint64_t)d.kept[i].host << 32) | i : ~0ull;
+    for (uint32_t i = n + threadIdx.x; i < P; i += blockDim.x) key[i] = ~0ull;
     lds_bitonic(key, P);
     const uint32_t m = n < cap ? n : cap;
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) out[i] = d.kept[(uint32_t)key[i]];
@@ -1839,8 +1891,14 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
       const uint32_t t0 = t * kSortTile;
       const uint32_t len = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
       const uint32_t P = pow2_at_least(len, 64u);
-      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x)
-        key[i] = i < len ? ((uint64_t)d.kept[t0 + i].host << 32) | (t0 + i) : ~0ull;
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        uint64_t k = ~0ull;
+        if (i < len) {
+          const uint32_t slot = kept_slot(pre, region, t0 + i);
+          k = ((uint64_t)d.kept[slot].host << 32) | slot;
+        }
+        key[i] = k;
+      }
       lds_bitonic(key, P);
       for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) d.skeys[t0 + i] = key[i];
       __syncthreads();  // key[] is rewritten by the next tile
@@ -1870,6 +1928,7 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
       if (rank < cap) out[rank] = d.kept[(uint32_t)k];
     }
   }
+  if (threadIdx.x == 0) c->n_kept = n;  // read by scan_finish in this same thread
   scan_finish(d, cap, info);
 }
 
@@ -1930,6 +1989,11 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
   const uint32_t c0 = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   // the first host is read before the count is known (in bounds: c0 < the list's capacity)
   const uint32_t x0 = c0 < (hosts ? n_hosts : d.cand_cap) ? src[c0] : 0u;
+  // in a scan (kEstWaves waves) wave c0 keeps its hosts in region c0 of the kept list, which
+  // holds every candidate it can get, and leaves their number in wave_kept[c0]: no counter
+  // shared between waves
+  const uint32_t region = kept_region(d.cand_cap);
+  uint32_t n_keep = 0;
   for (uint32_t c = c0; c < n; c += waves) {
     const uint32_t x = __builtin_amdgcn_readfirstlane(c == c0 ? x0 : src[c]);
     uint32_t U, feat;
@@ -1968,6 +2032,8 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       }
     }
     if (fabs(est - threshold) <= 1e-9 * threshold) flags |= SPS_F_NEAR;
+    // lane 0's decision (every lane computes the same estimate)
+    const bool keep = !direct && __builtin_amdgcn_readfirstlane(est >= threshold ? 1 : 0);
     if (lane == 0) {
       sps_result res;
       res.host = x;
@@ -1975,14 +2041,14 @@ __global__ void __launch_bounds__(256) k_estimate(Dev d, uint32_t cur, uint32_t 
       res.flags = flags;
       res.pad = 0;
       res.estimate = est;
-      if (direct) {
+      if (direct)
         direct[c] = res;
-      } else if (est >= threshold) {
-        const uint32_t pos = atomicAdd(&d.ctrl->n_kept, 1u);
-        if (pos < d.cand_cap) d.kept[pos] = res;
-      }
+      else if (keep)
+        d.kept[(uint64_t)c0 * region + n_keep] = res;
     }
+    n_keep += keep ? 1u : 0u;
   }
+  if (!direct && lane == 0) d.wave_kept[c0] = n_keep;
 }
 
 hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double threshold,
@@ -2054,8 +2120,9 @@ hipError_t launch_scan(const Dev& d, uint32_t cur, uint32_t window, double thres
   }
   {
     ProfScope ps(SPS_STAGE_ESTIMATE, st, ProfScope::kKernel);
-    launch_k(ps, k_estimate, dim3(n_cu * 2), dim3(256), 0, st, d, cur, lo, window, threshold,
-             mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr, rows_waves);
+    launch_k(ps, k_estimate, dim3(kEstWaves / (256 / kWave)), dim3(256), 0, st, d, cur, lo,
+             window, threshold, mlp, (const uint32_t*)nullptr, 0u, (sps_result*)nullptr,
+             rows_waves);
   }
   {
     ProfScope ps(SPS_STAGE_SORT, st, ProfScope::kKernel);
