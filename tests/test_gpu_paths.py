@@ -62,6 +62,27 @@ def test_report_at_candidate_capacity(cand_cap):
     g.close()
 
 
+@pytest.mark.parametrize("n_kept,n_dropped,cand_cap", [(2000, 1000, 3100), (4500, 1500, 6200)])
+def test_report_from_multi_entry_kept_regions(n_kept, n_dropped, cand_cap):
+    """More candidates than the estimate's 2048 waves, at capacities that give every wave a
+    kept-list region of 2 (4) entries, with candidates the filter drops mixed in (hosts with
+    4 peers are hot enough to be recovered but estimate below 8): the report, ordered in LDS
+    (2000 kept) or by tiles and ranks (4500 kept), equals the oracle's."""
+    rng = np.random.default_rng(n_kept)
+    hosts = rng.choice(1 << 32, n_kept + n_dropped, replace=False).astype(np.uint32)
+    dst = np.concatenate([np.repeat(hosts[:n_kept], 12), np.repeat(hosts[n_kept:], 4)])
+    src = rng.integers(0, 1 << 32, dst.size, dtype=np.uint64).astype(np.uint32)
+    p = np.stack([src, dst], 1)[rng.permutation(dst.size)]
+    params = dict(ORDER, cand_cap=cand_cap)
+    g, o = sps.Sketch(params), oracle.OracleSketch(params)
+    g.ingest(dev_pkts(p), 1)
+    o.ingest(p, 1)
+    print(f"[kept regions] {n_kept} + {n_dropped} hosts ingested, cand_cap {cand_cap}", flush=True)
+    got = assert_scan_equal(g, o, 1, 8.0, f"{n_kept} kept of {n_kept + n_dropped}")
+    assert len(got) > (4096 if n_kept > 4096 else 1024)  # the ordering path named above
+    g.close()
+
+
 def _crafted(params, hot_cols, cur=3, seed=0):
     """SRE state whose hot SREs are exactly hot_cols[i] in row i (three cells stamped `cur`,
     the hot cut for eta = 8), SLE array empty; the same state in a GPU and an oracle sketch."""
