@@ -1730,7 +1730,7 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
 // into the kept list, padded with keys above every host).  Every block first turns the
 // estimate waves' kept counts into the ordinal of each wave's first host (a prefix sum).
 //   n <= 1024: block 0 alone, one key per thread, a bitonic network in registers with
-//              cross-lane moves for partners closer than 64 and LDS beyond.
+//              cross-lane moves (DPP, permutes) for partners closer than 64 and LDS beyond.
 //   n <= 4096: block 0 alone, a bitonic sort of the whole list in LDS.
 //   n >  4096: every block sorts 4096-key tiles of the list in LDS and writes them to
 //              skeys; the last block to finish (a counter) then places every key at its
@@ -1832,6 +1832,36 @@ __device__ __forceinline__ uint32_t kept_slot(const uint32_t* pre, uint32_t regi
   return lo * region + (i - pre[lo]);
 }
 
+// The value of lane (this lane ^ J), J < 64: DPP within a quad (J = 1, 2) or a 16-lane row
+// (J = 4, 8; row_ror:n reads lane (l - n) mod 16), a cross-lane permute for 16 and 32.
+template <uint32_t J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // 1,0,3,2
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // 2,3,0,1
+  } else if constexpr (J == 4) {
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false);
+    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xF, 0xF, false);
+    return (lane_id() & 4u) ? dn : up;
+  } else if constexpr (J == 8) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+  } else {
+    return (uint32_t)__shfl_xor((int)v, (int)J, kWave);
+  }
+}
+
+// Stages J, J/2, ..., 1 of bitonic merge step k on one key per lane, in registers (the
+// partner distance is a compile-time constant, so every stage is one fixed exchange).
+template <uint32_t J>
+__device__ __forceinline__ void bitonic_lanes(uint64_t& v, uint32_t i, uint32_t k) {
+  const uint32_t lo = lane_xor<J>((uint32_t)v), hi = lane_xor<J>((uint32_t)(v >> 32));
+  const uint64_t w = ((uint64_t)hi << 32) | lo;
+  const bool up = (i & k) == 0u, lower = (i & J) == 0u;
+  v = (lower == up) ? (v < w ? v : w) : (v < w ? w : v);
+  if constexpr (J > 1) bitonic_lanes<J / 2>(v, i, k);
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
                                                             uint32_t cap,
                                                             uint32_t* __restrict__ info) {
@@ -1860,22 +1890,24 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
     const uint32_t P = pow2_at_least(n, 64u);
     const uint32_t i = threadIdx.x;
     uint64_t v = i < n ? key[i] : ~0ull;
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        uint64_t w;
-        if (j >= 64u) {
-          __syncthreads();  // the previous stage's readers are done
-          key[i] = v;
-          __syncthreads();
-          w = key[i ^ j];
-        } else {
-          const uint32_t lo = __shfl_xor((uint32_t)v, (int)j, kWave);
-          const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), (int)j, kWave);
-          w = ((uint64_t)hi << 32) | lo;
-        }
+    // merge steps k = 2 ... 64 within the wave, then k = 128 ... P: the stages with partners
+    // 64 or more lanes away through LDS, the rest within the wave
+    bitonic_lanes<1>(v, i, 2);
+    bitonic_lanes<2>(v, i, 4);
+    bitonic_lanes<4>(v, i, 8);
+    bitonic_lanes<8>(v, i, 16);
+    bitonic_lanes<16>(v, i, 32);
+    bitonic_lanes<32>(v, i, 64);
+    for (uint32_t k = 128; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j >= 64u; j >>= 1) {
+        __syncthreads();  // the previous stage's readers are done
+        key[i] = v;
+        __syncthreads();
+        const uint64_t w = key[i ^ j];
         const bool up = (i & k) == 0u, lower = (i & j) == 0u;
         v = (lower == up) ? (v < w ? v : w) : (v < w ? w : v);
       }
+      bitonic_lanes<32>(v, i, k);
     }
     const uint32_t m = n < cap ? n : cap;
     if (i < m) out[i] = d.kept[(uint32_t)v];
