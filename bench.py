@@ -478,6 +478,9 @@ def main():
     ap.add_argument("--accuracy-study", action="store_true",
                     help="only print the FPR/FNR/TFR table over windows 1, 5, 10, 20 and "
                          "thresholds 512, 1024, 2048 on the config-2 stream")
+    ap.add_argument("--merge-only", action="store_true",
+                    help="only run the config-3 leg (16 routers, batched ingest, merge, scan of "
+                         "the merged sketch) and print its JSON (for profiling its kernels)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -501,6 +504,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel()}), flush=True)
+        return
+    if args.merge_only:
+        print(json.dumps({"distributed_merge": merge_extra(log)}), flush=True)
         return
     rec, params, K_WIN, THETA = C2_RECIPE, C2_PARAMS, C2_WINDOW, C2_THRESHOLD
     t0 = time.perf_counter()

@@ -1,7 +1,7 @@
 """Summaries for profiles/ from rocprofv3 output (measurement tooling, not the product path).
 
     python profsum.py stats  <kernel_stats.csv> <out.md> "<title>" "<command>"
-    python profsum.py traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.md> "<commands>"
+    python profsum.py traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.md> "<commands>" ["<workload>" "<json path or empty>"]
     python profsum.py counters <out.md> "<title>" "<commands>" <pmc_dir> [<pmc_dir> ...]
 
 `traffic` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from two --pmc runs of the same
@@ -43,7 +43,8 @@ def _counter(d):
     return vals
 
 
-def traffic(fd, wd, cfd, cwd, out, cmds):
+def traffic(fd, wd, cfd, cwd, out, cmds, workload="config-2 workload",
+            json_out="profiles/traffic.json"):
     sys.path.insert(0, ROOT)
     from bench import kernel_source_hash
     fe, wr, cf, cw = _counter(fd), _counter(wd), _counter(cfd), _counter(cwd)
@@ -60,7 +61,7 @@ def traffic(fd, wd, cfd, cwd, out, cmds):
         js[k] = {"bytes_per_launch": int(f + w), "fetch_bytes": int(f), "write_bytes": int(w),
                     "dispatches": len(fe[k]), "source_hash": h}
         table.append(f"| `{k}` | {len(fe[k])} | {f / 1e6:.2f} | {w / 1e6:.2f} | {(f + w) / 1e6:.2f} |")
-    lines = ["# HBM traffic per launch, config-2 workload (rocprofv3 PMC)", "",
+    lines = [f"# HBM traffic per launch, {workload} (rocprofv3 PMC)", "",
              "Commands (repository root, one MI355X, ROCm 7.2):", "", "```", cmds, "```", "",
              f"Calibration: a 1 GiB device copy reads {cf['__amd_rocclr_copyBuffer'][0]:.0f} KiB in "
              f"FETCH_SIZE and {cw['__amd_rocclr_copyBuffer'][0]:.0f} KiB in WRITE_SIZE, so FETCH_SIZE "
@@ -68,7 +69,8 @@ def traffic(fd, wd, cfd, cwd, out, cmds):
              f"Kernel sources hash: `{h}`.", "",
              "| kernel | dispatches | fetch MB | write MB | total MB |", "|---|---|---|---|---|"] + table
     open(out, "w").write("\n".join(lines) + "\n")
-    json.dump(js, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    if json_out:  # the per-kernel bytes bench.py reports (config-2 kernels only)
+        json.dump(js, open(os.path.join(ROOT, json_out), "w"), indent=1)
 
 
 def _counters_all(d):
@@ -117,4 +119,4 @@ if __name__ == "__main__":
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], sys.argv[4], *sys.argv[5:])
     else:
-        traffic(*sys.argv[2:8])
+        traffic(*sys.argv[2:10])
