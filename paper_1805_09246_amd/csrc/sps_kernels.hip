@@ -1731,7 +1731,8 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
 // estimate waves' kept counts into the ordinal of each wave's first host (a prefix sum).
 //   n <= 1024: block 0 alone, one key per thread, a bitonic network in registers with
 //              cross-lane moves (DPP, permutes) for partners closer than 64 and LDS beyond.
-//   n <= 4096: block 0 alone, a bitonic sort of the whole list in LDS.
+//   n <= 4096: block 0 alone, the same network with two or four keys per thread (partners
+//              1024 or more keys apart in the same thread).
 //   n >  4096: every block sorts 4096-key tiles of the list in LDS and writes them to
 //              skeys; the last block to finish (a counter) then places every key at its
 //              rank: its position in its own tile plus, for every other tile, the number of
@@ -1862,6 +1863,64 @@ __device__ __forceinline__ void bitonic_lanes(uint64_t& v, uint32_t i, uint32_t 
   if constexpr (J > 1) bitonic_lanes<J / 2>(v, i, k);
 }
 
+// Ascending / descending compare-exchange of two keys held by one thread.
+__device__ __forceinline__ void key_cmpx(uint64_t& a, uint64_t& b, bool up) {
+  const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  a = up ? lo : hi;
+  b = up ? hi : lo;
+}
+
+// Bitonic sort of the first n (1024 < n <= S * 1024) keys of key[] by one block of 1024
+// threads: thread t holds keys s * 1024 + t (slot s < S) in registers.  Partners 1024 or more
+// keys apart are in the same thread, partners 64 ... 512 apart are exchanged through LDS,
+// closer ones within the wave.  Keys past n are padding above every key.
+template <uint32_t S>
+__device__ __forceinline__ void bitonic_slots(uint64_t* key, uint32_t n, uint64_t (&v)[S]) {
+  const uint32_t t = threadIdx.x;
+#pragma unroll
+  for (uint32_t s = 0; s < S; ++s) v[s] = s * 1024u + t < n ? key[s * 1024u + t] : ~0ull;
+#pragma unroll
+  for (uint32_t s = 0; s < S; ++s) {
+    const uint32_t x = s * 1024u + t;
+    bitonic_lanes<1>(v[s], x, 2);
+    bitonic_lanes<2>(v[s], x, 4);
+    bitonic_lanes<4>(v[s], x, 8);
+    bitonic_lanes<8>(v[s], x, 16);
+    bitonic_lanes<16>(v[s], x, 32);
+    bitonic_lanes<32>(v[s], x, 64);
+  }
+  for (uint32_t k = 128; k <= S * 1024u; k <<= 1) {
+    // slot pairs (s, s + j / 1024); the pair sorts ascending when key s * 1024 + t has bit k
+    // clear (t < 1024 < k here)
+    for (uint32_t j = k >> 1; j >= 1024u; j >>= 1) {
+      if (j == 2048u) {
+        if constexpr (S == 4) {
+          key_cmpx(v[0], v[2], true);
+          key_cmpx(v[1], v[3], (1024u & k) == 0u);
+        }
+      } else {
+        key_cmpx(v[0], v[1], true);
+        if constexpr (S == 4) key_cmpx(v[2], v[3], (2048u & k) == 0u);
+      }
+    }
+    for (uint32_t j = (k >> 1) < 512u ? (k >> 1) : 512u; j >= 64u; j >>= 1) {
+      __syncthreads();  // the previous stage's readers are done
+#pragma unroll
+      for (uint32_t s = 0; s < S; ++s) key[s * 1024u + t] = v[s];
+      __syncthreads();
+#pragma unroll
+      for (uint32_t s = 0; s < S; ++s) {
+        const uint32_t x = s * 1024u + t;
+        const uint64_t w = key[x ^ j];
+        const bool asc = (x & k) == 0u, lower = (x & j) == 0u;
+        v[s] = (lower == asc) ? (v[s] < w ? v[s] : w) : (v[s] < w ? w : v[s]);
+      }
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < S; ++s) bitonic_lanes<32>(v[s], s * 1024u + t, k);
+  }
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* __restrict__ out,
                                                             uint32_t cap,
                                                             uint32_t* __restrict__ info) {
@@ -1912,11 +1971,20 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
     const uint32_t m = n < cap ? n : cap;
     if (i < m) out[i] = d.kept[(uint32_t)v];
   } else if (out && !tiled) {
-    const uint32_t P = pow2_at_least(n, 64u);
-    for (uint32_t i = n + threadIdx.x; i < P; i += blockDim.x) key[i] = ~0ull;
-    lds_bitonic(key, P);
     const uint32_t m = n < cap ? n : cap;
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) out[i] = d.kept[(uint32_t)key[i]];
+    if (n <= 2048u) {
+      uint64_t v[2];
+      bitonic_slots<2>(key, n, v);
+#pragma unroll
+      for (uint32_t s = 0; s < 2u; ++s)
+        if (s * 1024u + threadIdx.x < m) out[s * 1024u + threadIdx.x] = d.kept[(uint32_t)v[s]];
+    } else {
+      uint64_t v[4];
+      bitonic_slots<4>(key, n, v);
+#pragma unroll
+      for (uint32_t s = 0; s < 4u; ++s)
+        if (s * 1024u + threadIdx.x < m) out[s * 1024u + threadIdx.x] = d.kept[(uint32_t)v[s]];
+    }
   } else if (tiled) {
     const uint32_t n_tiles = (n + kSortTile - 1) / kSortTile;
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
