@@ -1733,7 +1733,7 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
 //              cross-lane moves (DPP, permutes) for partners closer than 64 and LDS beyond.
 //   n <= 4096: block 0 alone, the same network with two or four keys per thread (partners
 //              1024 or more keys apart in the same thread).
-//   n >  4096: every block sorts 4096-key tiles of the list in LDS and writes them to
+//   n >  4096: every block sorts 4096-key tiles with that network and writes them to
 //              skeys; the last block to finish (a counter) then places every key at its
 //              rank: its position in its own tile plus, for every other tile, the number of
 //              smaller keys there (a binary search).
@@ -1743,26 +1743,6 @@ __device__ float mlp_forward_wave(const float* __restrict__ w, float in_lane) {
 constexpr int kSortThreads = 1024;
 constexpr int kSortTile = 4096;
 constexpr uint32_t kSortMaxBlocks = 16;  // blocks of the sort (tiles taken round robin)
-
-// Bitonic sort of the first P (a power of two, 64 <= P <= kSortTile) keys in LDS.
-__device__ __forceinline__ void lds_bitonic(uint64_t* key, uint32_t P) {
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-        const uint32_t l = i ^ j;
-        if (l > i) {
-          const uint64_t a = key[i], b = key[l];
-          if ((a > b) == ((i & k) == 0)) {
-            key[i] = b;
-            key[l] = a;
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
 
 __device__ __forceinline__ uint32_t pow2_at_least(uint32_t n, uint32_t lo) {
   uint32_t P = lo;
@@ -1990,17 +1970,16 @@ __global__ void __launch_bounds__(kSortThreads) k_rank_sort(Dev d, sps_result* _
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
       const uint32_t t0 = t * kSortTile;
       const uint32_t len = n - t0 < (uint32_t)kSortTile ? n - t0 : (uint32_t)kSortTile;
-      const uint32_t P = pow2_at_least(len, 64u);
-      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-        uint64_t k = ~0ull;
-        if (i < len) {
-          const uint32_t slot = kept_slot(pre, region, t0 + i);
-          k = ((uint64_t)d.kept[slot].host << 32) | slot;
-        }
-        key[i] = k;
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint32_t slot = kept_slot(pre, region, t0 + i);
+        key[i] = ((uint64_t)d.kept[slot].host << 32) | slot;
       }
-      lds_bitonic(key, P);
-      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) d.skeys[t0 + i] = key[i];
+      __syncthreads();
+      uint64_t v[4];
+      bitonic_slots<4>(key, len, v);
+#pragma unroll
+      for (uint32_t s = 0; s < 4u; ++s)
+        if (s * 1024u + threadIdx.x < len) d.skeys[t0 + s * 1024u + threadIdx.x] = v[s];
       __syncthreads();  // key[] is rewritten by the next tile
     }
     // release this block's tiles, then count it; the last block goes on alone
