@@ -33,10 +33,11 @@ ORDER = dict(q=17, r=10, delta=2, eta=8, qp=12, rp=3, etap=64, deltap=64, theta=
              anet_side=0, seed=41)
 
 
-@pytest.mark.parametrize("n_hosts", [1100, 4096, 4097, 10000])
+@pytest.mark.parametrize("n_hosts", [1100, 3000, 4096, 4097, 10000])
 def test_report_order_paths(n_hosts):
-    """1100 and 4096 kept hosts: one block sorts them in LDS; 4097 and 10000: 4096-key tiles
-    sorted by every block, then placed by rank.  Every host has 12 peers (tau = 0, so all are
+    """1100, 3000 and 4096 kept hosts: one block sorts them with two (1100) or four keys per
+    thread, padded above the hosts (3000); 4097 and 10000: 4096-key tiles sorted by every
+    block, then placed by rank.  Every host has 12 peers (tau = 0, so all are
     sampled) and is reported; the whole report equals the oracle's."""
     p = _hosts_with_peers(n_hosts, 12, n_hosts)
     g, o = sps.Sketch(ORDER), oracle.OracleSketch(ORDER)
